@@ -1,0 +1,482 @@
+/*
+ * causal_oracle.c -- plain, slow, obviously correct CPU oracle for the causal-set
+ * interval-abundance path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the reference the GPU library is checked
+ * against.  Only the test suite, the smoke check and the benchmark's CPU-baseline
+ * leg may load it.  It shares no code, header, table or constant generator with
+ * the GPU library; every definition below is written out from the thesis
+ * (W. J. Cunningham, "High Performance Algorithms for Quantum Gravity and
+ * Cosmology", 2018) or from the published definition of the generator it uses.
+ *
+ * What it computes, and where each piece is defined:
+ *   sprinkle      App. A, "Causal Set Sprinklings": 1+1 Minkowski diamond
+ *                 (u, v uniform), 3+1 Minkowski diamond (here by rejection from the
+ *                 bounding box), 3+1 de Sitter slab with spherical foliation
+ *                 (density sec^4(eta) in conformal time, uniform on S^3).
+ *   time order    Sec. 3.2 "Pairwise Relations": elements are labelled so that a
+ *                 later index never precedes an earlier one.
+ *   causal matrix Ch. 4 introduction: i and j are related when timelike
+ *                 separated; stored as P + P^T (Sec. 3.2 "Data Structures").
+ *   abundances    Alg. "Naive Interval Abundance Measurement" and the
+ *                 inclusive-order-interval definition (eq. IOIs): for every related
+ *                 pair count the elements strictly inside its Alexandroff set.
+ *   fast tier     Alg. "Optimized Interval Abundance Measurement": word-wise AND
+ *                 + popcount over the columns strictly between i and j.
+ *   action        Sec. 4.2: local BD actions S^(1+1), S^(3+1) and their smeared
+ *                 forms S_eps with the smearing functions f_2 and f_4.
+ *
+ * Parity pins (see tests/test_oracle_*.py): generator test vector, brute-force
+ * enumeration of all 2D orders on tiny sets, closed forms (chains, antichains,
+ * disjoint chains), exact invariants (sum N_n = R, sum n N_n = sum indeg*outdeg),
+ * the numpy C@C special case, statistical moments (ordering fractions 1/4 and
+ * 1/10, 4D acceptance pi/24, conformal-time marginal), and exact rational
+ * evaluation of the smeared sums.
+ *
+ * Compiled with -O2 -fopenmp -ffp-contract=off: no fused multiply-add, so every
+ * floating-point predicate is the exact sequence of IEEE operations written here.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+/* Region codes (same numeric values as the GPU library's public enumeration). */
+enum { OR_MINK2_DIAMOND = 0, OR_MINK4_DIAMOND = 1, OR_DS4_SLAB = 2 };
+
+/* ------------------------------------------------------------------------- */
+/* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014), as in the public-domain       */
+/* reference next(): state += 0x9E3779B97F4A7C15, then the output mix below.   */
+/* ------------------------------------------------------------------------- */
+static const uint64_t OR_GOLDEN = 0x9E3779B97F4A7C15ULL;
+
+static uint64_t or_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* The published sequential generator: advance the state, return the mix. */
+uint64_t or_splitmix64_next(uint64_t *state)
+{
+    *state += OR_GOLDEN;
+    return or_mix(*state);
+}
+
+/* Output number c (0-based) of a SplitMix64 generator started at `state`:
+ * calling next() c+1 times leaves state + (c+1)*golden, so this is a jump. */
+static uint64_t or_output(uint64_t state, uint64_t c)
+{
+    return or_mix(state + (c + 1) * OR_GOLDEN);
+}
+
+/* Stream key: output `stream` of the generator started at output 0 of the
+ * generator started at `seed`. */
+static uint64_t or_stream_key(uint64_t seed, uint64_t stream)
+{
+    return or_output(or_output(seed, 0), stream);
+}
+
+uint64_t or_draw(uint64_t seed, uint64_t stream, uint64_t c)
+{
+    return or_output(or_stream_key(seed, stream), c);
+}
+
+/* Uniform on [0,1): top 53 bits times 2^-53 (exact). */
+static double or_unit(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
+
+/* ------------------------------------------------------------------------- */
+/* Sprinkling                                                                  */
+/* ------------------------------------------------------------------------- */
+
+int or_coord_planes(int region)
+{
+    switch (region) {
+    case OR_MINK2_DIAMOND: return 2;  /* u, v                         */
+    case OR_MINK4_DIAMOND: return 4;  /* t, x, y, z                   */
+    case OR_DS4_SLAB:      return 7;  /* tan eta, cos eta, sin eta, n0..n3 on S^3 */
+    default:               return -1;
+    }
+}
+
+typedef struct { uint64_t key; int64_t gen; } or_sortkey;
+
+static int or_cmp_key(const void *a, const void *b)
+{
+    const or_sortkey *x = (const or_sortkey *)a, *y = (const or_sortkey *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    if (x->gen != y->gen) return x->gen < y->gen ? -1 : 1;
+    return 0;
+}
+
+/* Monotone map of a double onto uint64 so that unsigned order = numeric order
+ * (negative numbers: all bits flipped; non-negative: sign bit set). */
+static uint64_t or_order_bits(double x)
+{
+    uint64_t b;
+    memcpy(&b, &x, sizeof b);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ULL);
+}
+
+/*
+ * Sprinkle n points into the region and label them in time order.
+ * Output: SoA planes, coords[p*n + i] for plane p, sorted.
+ * eta0 is used by the de Sitter slab only (eta in [-eta0, eta0]).
+ * Returns 0 on success, -1 on bad arguments.
+ */
+int or_sprinkle(int region, double eta0, uint64_t seed, int64_t n, double *coords)
+{
+    int planes = or_coord_planes(region);
+    if (planes < 0 || n < 1) return -1;
+    double *raw = (double *)malloc(sizeof(double) * (size_t)planes * (size_t)n);
+    or_sortkey *keys = (or_sortkey *)malloc(sizeof(or_sortkey) * (size_t)n);
+    if (!raw || !keys) { free(raw); free(keys); return -1; }
+
+    if (region == OR_MINK2_DIAMOND) {
+        /* 1+1 diamond, u0 = v0 = 1: u = U, v = U (App. A).  Time order by the
+         * exact integer u+v (scaled by 2^53); a related pair has both u and v
+         * larger, hence a strictly larger key. */
+        uint64_t s = or_stream_key(seed, 0);
+        for (int64_t g = 0; g < n; g++) {
+            uint64_t ku = or_output(s, 2 * (uint64_t)g) >> 11;
+            uint64_t kv = or_output(s, 2 * (uint64_t)g + 1) >> 11;
+            raw[0 * n + g] = (double)ku * 0x1.0p-53;
+            raw[1 * n + g] = (double)kv * 0x1.0p-53;
+            keys[g].key = ku + kv;
+            keys[g].gen = g;
+        }
+    } else if (region == OR_MINK4_DIAMOND) {
+        /* Alexandrov interval of height 1 between (0,0,0,0) and (1,0,0,0):
+         * candidates uniform in [0,1) x [-1/2,1/2)^3, accepted when the spatial
+         * radius is inside both cones: x^2+y^2+z^2 < min(t, 1-t)^2.  The first n
+         * accepted candidates, in candidate order, are kept. */
+        uint64_t s = or_stream_key(seed, 1);
+        int64_t got = 0;
+        for (uint64_t c = 0; got < n; c++) {
+            uint64_t kt = or_output(s, 4 * c) >> 11;
+            double t = (double)kt * 0x1.0p-53;
+            double x = or_unit(or_output(s, 4 * c + 1)) - 0.5;
+            double y = or_unit(or_output(s, 4 * c + 2)) - 0.5;
+            double z = or_unit(or_output(s, 4 * c + 3)) - 0.5;
+            double r = t < 1.0 - t ? t : 1.0 - t;
+            double rr = x * x + y * y;
+            rr = rr + z * z;
+            if (rr < r * r) {
+                raw[0 * n + got] = t;
+                raw[1 * n + got] = x;
+                raw[2 * n + got] = y;
+                raw[3 * n + got] = z;
+                keys[got].key = kt;
+                keys[got].gen = got;
+                got++;
+            }
+        }
+    } else {
+        /* 3+1 de Sitter slab, spherical foliation, eta in [-eta0, eta0]:
+         * the conformal-time density is proportional to sec^4(eta).  With
+         * x = tan(eta), sec^4(eta) d(eta) = (1 + x^2) dx, so the CDF is linear
+         * in x + x^3/3 and the inverse is the real root of the cubic
+         * x^3 + 3x - 3y = 0:  x = 2 sinh(asinh(3y/2)/3).
+         * The S^3 direction is a cube-rejected point of B^4, normalised. */
+        double X = tan(eta0);
+        double Y = X + ((X * X) * X) / 3.0;
+        uint64_t sx = or_stream_key(seed, 2);
+        uint64_t sn = or_stream_key(seed, 3);
+        for (int64_t g = 0; g < n; g++) {
+            double u = or_unit(or_output(sx, (uint64_t)g));
+            double y = (2.0 * u - 1.0) * Y;
+            double x = 2.0 * sinh(asinh(1.5 * y) / 3.0);
+            double c = 1.0 / sqrt(1.0 + x * x);
+            double sn_eta = x * c;
+            uint64_t ps = or_output(sn, (uint64_t)g);  /* per-point generator state */
+            double a[4], r2;
+            uint64_t k = 0;
+            for (;;) {
+                for (int q = 0; q < 4; q++)
+                    a[q] = 2.0 * or_unit(or_output(ps, 4 * k + (uint64_t)q)) - 1.0;
+                r2 = a[0] * a[0] + a[1] * a[1];
+                r2 = r2 + a[2] * a[2];
+                r2 = r2 + a[3] * a[3];
+                k++;
+                if (r2 < 1.0 && r2 > 0x1.0p-40) break;
+            }
+            double r = sqrt(r2);
+            raw[0 * n + g] = x;
+            raw[1 * n + g] = c;
+            raw[2 * n + g] = sn_eta;
+            for (int q = 0; q < 4; q++) raw[(3 + q) * n + g] = a[q] / r;
+            keys[g].key = or_order_bits(x);
+            keys[g].gen = g;
+        }
+    }
+
+    qsort(keys, (size_t)n, sizeof(or_sortkey), or_cmp_key);
+    for (int64_t i = 0; i < n; i++)
+        for (int p = 0; p < planes; p++)
+            coords[(int64_t)p * n + i] = raw[(int64_t)p * n + keys[i].gen];
+    free(raw);
+    free(keys);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Causal relation (strict: null and equal-time pairs are unrelated)          */
+/* ------------------------------------------------------------------------- */
+
+/* Is i ≺ j?  Only asked with i < j in time order. */
+static int or_related(int region, const double *c, int64_t n, int64_t i, int64_t j)
+{
+    if (region == OR_MINK2_DIAMOND) {
+        return c[i] < c[j] && c[n + i] < c[n + j];
+    } else if (region == OR_MINK4_DIAMOND) {
+        double dt = c[j] - c[i];
+        if (!(dt > 0.0)) return 0;
+        double dx = c[n + j] - c[n + i];
+        double dy = c[2 * n + j] - c[2 * n + i];
+        double dz = c[3 * n + j] - c[3 * n + i];
+        double s = dx * dx + dy * dy;
+        s = s + dz * dz;
+        return dt * dt > s;
+    } else {
+        /* Delta eta > great-circle angle  <=>  cos(Delta eta) < n_i . n_j, valid
+         * because both angles lie in [0, pi] (Delta eta <= 2 eta0 < pi). */
+        if (!(c[i] < c[j])) return 0;
+        double cdeta = c[n + i] * c[n + j] + c[2 * n + i] * c[2 * n + j];
+        double dot = c[3 * n + i] * c[3 * n + j] + c[4 * n + i] * c[4 * n + j];
+        dot = dot + c[5 * n + i] * c[5 * n + j];
+        dot = dot + c[6 * n + i] * c[6 * n + j];
+        return cdeta < dot;
+    }
+}
+
+int64_t or_ld_words(int64_t n) { return ((n + 511) / 512) * 8; }
+
+/* Symmetric causal matrix S = C + C^T as packed rows: bit j of row i is
+ * bit (j & 63) of word i*ld + (j >> 6).  Row by row, each pair tested with the
+ * earlier element first, so every row is written by exactly one thread. */
+int or_causal_matrix(int region, const double *coords, int64_t n, uint64_t *bits, int64_t ld)
+{
+    if (or_coord_planes(region) < 0 || n < 1 || ld * 64 < n) return -1;
+    memset(bits, 0, sizeof(uint64_t) * (size_t)n * (size_t)ld);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        uint64_t *row = bits + i * ld;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            int r = i < j ? or_related(region, coords, n, i, j)
+                          : or_related(region, coords, n, j, i);
+            if (r) row[j >> 6] |= 1ULL << (j & 63);
+        }
+    }
+    return 0;
+}
+
+static int or_bit(const uint64_t *bits, int64_t ld, int64_t i, int64_t j)
+{
+    return (int)((bits[i * ld + (j >> 6)] >> (j & 63)) & 1ULL);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Interval abundances                                                         */
+/* ------------------------------------------------------------------------- */
+
+/* Alg. "Naive Interval Abundance Measurement": for each related i < j count
+ * the k with i < k < j, i ≺ k and k ≺ j; bin that count.  hist has n-1 bins
+ * (counts 0..n-2; the thesis's n_m is hist[m-1]).  The pair loop is split over
+ * threads by i with one private histogram per thread, then reduced. */
+int or_histogram_naive(const uint64_t *bits, int64_t n, int64_t ld, uint64_t *hist)
+{
+    if (n < 2) return -1;
+    int64_t nb = n - 1;
+    memset(hist, 0, sizeof(uint64_t) * (size_t)nb);
+#pragma omp parallel
+    {
+        uint64_t *mine = (uint64_t *)calloc((size_t)nb, sizeof(uint64_t));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < n - 1; i++) {
+            for (int64_t j = i + 1; j < n; j++) {
+                if (!or_bit(bits, ld, i, j)) continue;
+                int64_t x = 0;
+                for (int64_t k = i + 1; k < j; k++)
+                    if (or_bit(bits, ld, i, k) && or_bit(bits, ld, k, j)) x++;
+                mine[x]++;
+            }
+        }
+#pragma omp critical
+        for (int64_t m = 0; m < nb; m++) hist[m] += mine[m];
+        free(mine);
+    }
+    return 0;
+}
+
+/* Interval size of one pair by word AND + popcount over columns (i, j). */
+int64_t or_pair_interval(const uint64_t *bits, int64_t ld, int64_t i, int64_t j)
+{
+    int64_t lo = i + 1, hi = j; /* columns [lo, hi) */
+    if (lo >= hi) return 0;
+    const uint64_t *a = bits + i * ld, *b = bits + j * ld;
+    int64_t w0 = lo >> 6, w1 = (hi - 1) >> 6;
+    int64_t x = 0;
+    for (int64_t w = w0; w <= w1; w++) {
+        uint64_t m = ~0ULL;
+        if (w == w0) m &= ~0ULL << (lo & 63);
+        if (w == w1) m &= ~0ULL >> (63 - ((hi - 1) & 63));
+        x += __builtin_popcountll(a[w] & b[w] & m);
+    }
+    return x;
+}
+
+/* Alg. "Optimized Interval Abundance Measurement" on the CPU, restricted to
+ * rows i in [row_begin, row_end) (the full histogram for 0..n-1).  Private
+ * per-thread histograms are summed at the end. Returns the pairs counted. */
+int64_t or_histogram_fast(const uint64_t *bits, int64_t n, int64_t ld, uint64_t *hist,
+                          int64_t row_begin, int64_t row_end)
+{
+    if (n < 2 || row_begin < 0 || row_end > n || row_begin > row_end) return -1;
+    int64_t nb = n - 1, pairs = 0;
+    memset(hist, 0, sizeof(uint64_t) * (size_t)nb);
+#pragma omp parallel reduction(+ : pairs)
+    {
+        uint64_t *mine = (uint64_t *)calloc((size_t)nb, sizeof(uint64_t));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = row_begin; i < row_end; i++) {
+            for (int64_t j = i + 1; j < n; j++) {
+                if (!or_bit(bits, ld, i, j)) continue;
+                mine[or_pair_interval(bits, ld, i, j)]++;
+                pairs++;
+            }
+        }
+#pragma omp critical
+        for (int64_t m = 0; m < nb; m++) hist[m] += mine[m];
+        free(mine);
+    }
+    return pairs;
+}
+
+/* In- and out-degrees (past and future set sizes) of every element and the
+ * number of 3-chains i ≺ k ≺ j, which equals sum_n n*N_n. */
+int or_degrees(const uint64_t *bits, int64_t n, int64_t ld, int64_t *indeg, int64_t *outdeg,
+               uint64_t *chains3, uint64_t *relations)
+{
+    uint64_t c3 = 0, rel = 0;
+#pragma omp parallel for reduction(+ : c3, rel) schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        int64_t in = 0, out = 0;
+        for (int64_t j = 0; j < n; j++) {
+            if (!or_bit(bits, ld, i, j)) continue;
+            if (j < i) in++; else out++;
+        }
+        indeg[i] = in;
+        outdeg[i] = out;
+        c3 += (uint64_t)in * (uint64_t)out;
+        rel += (uint64_t)out;
+    }
+    *chains3 = c3;
+    *relations = rel;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Benincasa-Dowker action in quadruple precision                              */
+/* ------------------------------------------------------------------------- */
+typedef __float128 q_t;
+
+static q_t q_sqrt(q_t a)   /* Newton from the double root; two steps reach quad */
+{
+    if (a <= 0) return 0;
+    q_t r = (q_t)sqrt((double)a);
+    r = (r + a / r) / 2;
+    r = (r + a / r) / 2;
+    r = (r + a / r) / 2;
+    return r;
+}
+
+static q_t q_powi(q_t b, int64_t e)  /* b^e, e >= 0, with 0^0 = 1 */
+{
+    q_t r = 1;
+    while (e > 0) {
+        if (e & 1) r *= b;
+        b *= b;
+        e >>= 1;
+    }
+    return r;
+}
+
+/* Smearing functions written as sum_k c_k(n) eps^k (1-eps)^(n-k), k <= min(n, K):
+ * the thesis's f_d(n, eps) multiplied out, so no power of (1-eps) is negative
+ * and eps = 1 is allowed (then f reduces to the local coefficients).
+ *   f_2: c_0 = 1, c_1 = -2n, c_2 = n(n-1)/2
+ *   f_4: c_0 = 1, c_1 = -9n, c_2 = 8n(n-1), c_3 = -(4/3) n(n-1)(n-2) */
+static q_t or_smear(int dim, int64_t n, q_t eps)
+{
+    q_t nn = (q_t)n, c[4];
+    int K;
+    if (dim == 2) {
+        c[0] = 1; c[1] = -2 * nn; c[2] = nn * (nn - 1) / 2; K = 2;
+    } else {
+        c[0] = 1; c[1] = -9 * nn; c[2] = 8 * nn * (nn - 1);
+        c[3] = -(q_t)4 * nn * (nn - 1) * (nn - 2) / 3; K = 3;
+    }
+    q_t f = 0, om = 1 - eps;
+    for (int k = 0; k <= K && k <= n; k++)
+        f += c[k] * q_powi(eps, k) * q_powi(om, n - k);
+    return f;
+}
+
+/*
+ * Action from the abundances hist[0..n-2] (hist[m] = N_m, pairs with m elements
+ * inside).  dim 2 or 4.  eps == 0 selects the local action:
+ *   S^(1+1) = 2 (N - 2N_0 + 4N_1 - 2N_2)
+ *   S^(3+1) = (4/sqrt 6) (N - N_0 + 9N_1 - 16N_2 + 8N_3)        (l = l_p)
+ * 0 < eps <= 1 selects the smeared action:
+ *   S_eps^(1+1) = 2 eps [N - 2 eps sum_m N_m f_2(m, eps)]
+ *   S_eps^(3+1) = 4 sqrt(eps/6) [N - eps sum_m N_m f_4(m, eps)]
+ * Out: *out = S rounded once to double; *kappa = (N + eps_c sum|N_m f_m|)/|bracket|
+ * (1 for the local action).  Returns 0, or -1 on bad arguments.
+ */
+int or_action(const uint64_t *hist, int64_t n, int dim, double eps, double *out, double *kappa)
+{
+    if (n < 2 || (dim != 2 && dim != 4) || eps < 0.0 || eps > 1.0) return -1;
+    int64_t nb = n - 1;
+    if (eps == 0.0) {
+        int64_t h[4] = {0, 0, 0, 0};
+        for (int m = 0; m < 4 && m < nb; m++) h[m] = (int64_t)hist[m];
+        q_t s;
+        if (dim == 2) {
+            int64_t I = n - 2 * h[0] + 4 * h[1] - 2 * h[2];
+            s = 2 * (q_t)I;
+        } else {
+            int64_t I = n - h[0] + 9 * h[1] - 16 * h[2] + 8 * h[3];
+            s = 4 / q_sqrt(6) * (q_t)I;
+        }
+        *out = (double)s;
+        if (kappa) *kappa = 1.0;
+        return 0;
+    }
+    q_t e = (q_t)eps, sum = 0, asum = 0;
+    for (int64_t m = 0; m < nb; m++) {
+        if (!hist[m]) continue;
+        q_t t = (q_t)hist[m] * or_smear(dim, m, e);
+        sum += t;
+        asum += t < 0 ? -t : t;
+    }
+    q_t ec = dim == 2 ? 2 * e : e;
+    q_t bracket = (q_t)n - ec * sum;
+    q_t pref = dim == 2 ? 2 * e : 4 * q_sqrt(e / 6);
+    *out = (double)(pref * bracket);
+    if (kappa) {
+        q_t ab = bracket < 0 ? -bracket : bracket;
+        *kappa = ab > 0 ? (double)(((q_t)n + ec * asum) / ab) : INFINITY;
+    }
+    return 0;
+}
+
+/* The smearing weight itself, rounded to double (for tests). */
+double or_smear_weight(int dim, int64_t m, double eps)
+{
+    return (double)or_smear(dim, m, (q_t)eps);
+}
+
+int or_max_threads(void) { return omp_get_max_threads(); }

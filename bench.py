@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the causal-set interval-abundance path on one MI355X.
+
+A step is one pass of the whole path over one synthetic causal set:
+sprinkle (N points, time order) -> causal matrix -> interval histogram (MFMA counter)
+-> actions (local and smeared for each eps).  Default workload: the 3+1 Minkowski
+diamond of height 1 with N = 131072, eps in {0.05, 0.1, 0.2}.
+
+Printed JSON line (rank 0 only):
+  value        related-pair interval counts per second of whole steps, R / t_step
+  roofline     the MFMA counter kernel: useful int8 ops 2 * N(N-1)(N-2)/6 per launch
+               over its mean duration from HIP events on the launch stream, against
+               the MI355X dense int8 peak (5.0 POP/s)
+  bitset       the VALU bitset counter on the same matrix (R / t, and bit-pairs/s)
+  batch        256 1+1 diamonds of N in [512, 8192]: ensembles/s in one graph launch
+               against 256 per-instance launch sequences
+  cpu_baseline the CPU oracle's optimised tier timed on a row sample of the same matrix
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+PEAK_INT8_OPS = 5.0e15
+PEAK_VALU_BITPAIRS = 256 * 4 * 16 * 2.4e9 * 16  # 2 VALU ops per 32 bit-pairs (AND, BCNT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="mink4_n131072", choices=sorted(
+        k for k in W.WORKLOADS if not k.startswith("batch")))
+    ap.add_argument("--no-bitset", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU work for the oracle sample")
+    return ap.parse_args()
+
+
+def events_ms(pairs):
+    return [a.elapsed_time(b) for a, b in pairs]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: every box here has one MI355X and the path is "
+              "not sharded across GPUs; run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_1805_04463_amd as cs
+
+    cfg = W.WORKLOADS[args.workload]
+    region, n, seed, eps_list = cfg["region"], cfg["n"], cfg["seed"], tuple(cfg["eps"])
+    dim = W.REGION_DIM[region]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    # Preallocated device buffers: the timed region allocates nothing.
+    planes = cs.cs_coord_planes(region)
+    ld = cs.cs_ld_words(n)
+    L = cs.lib()
+    coords = torch.empty((planes, n), dtype=torch.float64, device=dev)
+    bits = torch.empty((n, ld), dtype=torch.int64, device=dev)
+    hist = torch.empty(n - 1, dtype=torch.int64, device=dev)
+    acts = torch.empty(1 + len(eps_list), dtype=torch.float64, device=dev)
+    sp_ws = torch.empty(L.cs_sprinkle_workspace_bytes(region, n), dtype=torch.uint8, device=dev)
+    hist_ws = {c: torch.empty(L.cs_histogram_workspace_bytes(n, c), dtype=torch.uint8, device=dev)
+               for c in (cs.CS_COUNT_MFMA, cs.CS_COUNT_BITSET)}
+    eta0 = W.DS_ETA0
+
+    def step(counter, ev=None):
+        sp_coords = coords
+        cs.binding._check(L.cs_sprinkle(region, eta0, seed, n, cs.binding._ptr(sp_coords),
+                                        cs.binding._ptr(sp_ws), sp_ws.numel(),
+                                        cs.binding._stream(stream)), "sprinkle")
+        cs.cs_causal_matrix(region, coords, n, ld, out=bits, stream=stream)
+        if ev is not None:
+            ev[0].record(stream)
+        cs.cs_interval_histogram(bits, n, counter, out=hist, workspace=hist_ws[counter],
+                                 stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        cs.cs_action(hist, n, dim, 0.0, out=acts[0:1], stream=stream)
+        for k, e in enumerate(eps_list):
+            cs.cs_action(hist, n, dim, e, out=acts[k + 1:k + 2], stream=stream)
+
+    for _ in range(args.warmup):
+        step(cs.CS_COUNT_MFMA)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(cs.CS_COUNT_MFMA, evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    count_ms = events_ms(evs)
+    h = hist.cpu().numpy().view(np.uint64)
+    R = int(h.sum())
+    useful_macs = n * (n - 1) * (n - 2) // 6
+    achieved = 2 * useful_macs / (np.mean(count_ms) * 1e-3)
+    actions = acts.cpu().tolist()
+
+    out = {
+        "metric": "related-pair interval counts/sec (4D, N=131072), MFMA vs bitset; ensembles/sec",
+        "value": R / (ms_step * 1e-3),
+        "unit": "related-pair counts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8-mfma/int32 counts, fp64 coordinates and action",
+        "data": "synthetic sprinkling (seeded counter-based SplitMix64), no dataset",
+        "config": {"workload": args.workload, "region": W.REGION_NAMES[region], "n": n,
+                   "seed": seed, "eps": list(eps_list), "counter": "mfma"},
+        "relations": R,
+        "count_kernel_ms": {"mean": float(np.mean(count_ms)), "min": float(np.min(count_ms))},
+        "counts_per_s_kernel": R / (np.mean(count_ms) * 1e-3),
+        "actions": {"local": actions[0], **{f"eps={e}": a for e, a in zip(eps_list, actions[1:])}},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_INT8_OPS / 1e12,
+                     "unit": "TOP/s", "frac": achieved / PEAK_INT8_OPS, "traffic": None,
+                     "kernel": "k_count_mfma<4>",
+                     "work_per_launch": f"2*N(N-1)(N-2)/6 = {2 * useful_macs:.4e} int8 ops"},
+    }
+
+    if not args.no_bitset:
+        bev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(2)]
+        for k in range(2):
+            bev[k][0].record(stream)
+            cs.cs_interval_histogram(bits, n, cs.CS_COUNT_BITSET, out=hist,
+                                     workspace=hist_ws[cs.CS_COUNT_BITSET], stream=stream)
+            bev[k][1].record(stream)
+        torch.cuda.synchronize()
+        hb = hist.cpu().numpy().view(np.uint64)
+        bms = min(events_ms(bev))
+        out["bitset"] = {"count_kernel_ms": bms, "counts_per_s_kernel": R / (bms * 1e-3),
+                         "useful_bitpairs_per_s": useful_macs / (bms * 1e-3),
+                         "frac_valu_peak": useful_macs / (bms * 1e-3) / PEAK_VALU_BITPAIRS,
+                         "identical_to_mfma": bool(np.array_equal(hb, h)),
+                         "mfma_speedup": bms / float(np.min(count_ms))}
+
+    if not args.no_batch and hasattr(L, "cs_batch_run"):
+        from bench_batch import run_batch  # noqa: E402  (batch leg lives beside this file)
+        out["batch"] = run_batch(cs, torch, dev, stream)
+
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        # The oracle sprinkles and links on its own; nothing is taken from the GPU.
+        tm = time.perf_counter()
+        c_np = oracle.sprinkle(region, n, seed, eta0)
+        b_np = oracle.causal_matrix(region, c_np)
+        t_link = time.perf_counter() - tm
+        del c_np
+        # Rows spread evenly over the set; pilot sample sizes the real one.
+        pilot = np.linspace(0, n - 2, 16).astype(np.int64)
+        tp = time.perf_counter()
+        _, pp = oracle.histogram_fast_rows(b_np, n, pilot)
+        tpil = time.perf_counter() - tp
+        nrows = int(np.clip(16 * args.cpu_seconds / max(tpil, 1e-3), 16, n - 1))
+        rows = np.linspace(0, n - 2, nrows).astype(np.int64)
+        tc = time.perf_counter()
+        _, pairs = oracle.histogram_fast_rows(b_np, n, rows)
+        tcpu = time.perf_counter() - tc
+        out["cpu_baseline"] = {"value": pairs / tcpu, "unit": "related-pair counts/s",
+                               "cores": oracle.max_threads(), "kind": "oracle",
+                               "sample": f"optimised-tier oracle (word AND + popcount) over "
+                                         f"{nrows} evenly spaced rows of the same N={n} matrix: "
+                                         f"{pairs} related pairs in {tcpu:.1f} s "
+                                         f"(oracle sprinkle + matrix took {t_link:.1f} s)"}
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,163 @@
+/*
+ * causal.h -- C ABI of the MI355X causal-set interval-abundance library (libcausal.so).
+ *
+ * The library computes, on one AMD Instinct MI355X (gfx950), the data-parallel path of
+ * the causal-set action pipeline of W. J. Cunningham, "High Performance Algorithms for
+ * Quantum Gravity and Cosmology" (2018):
+ *
+ *   cs_sprinkle            N points uniform in a spacetime region, labelled in time order
+ *                          (App. A "Causal Set Sprinklings"; Sec. 3.2 "Pairwise Relations")
+ *   cs_causal_matrix       the causal matrix as packed symmetric bitset rows P + P^T
+ *                          (Sec. 3.2 "Data Structures for Graphs"; Ch. 4 introduction)
+ *   cs_interval_histogram  interval abundances N_n (eq. IOIs; algorithms "Naive" and
+ *                          "Optimized Interval Abundance Measurement"), two counters
+ *   cs_action              Benincasa-Dowker action, local or smeared (Sec. 4.2)
+ *   cs_batch_*             the four steps for an ensemble of independent 1+1 diamonds in
+ *                          one persistent launch per step, capturable in a HIP graph
+ *
+ * Conventions for every entry point:
+ *   - Pointers named "device" are caller-owned device memory (hipMalloc, or a torch CUDA
+ *     tensor on ROCm).  The library never frees or retains caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Calls only
+ *     validate arguments on the host and enqueue work; they return before it finishes.
+ *   - Errors are returned synchronously as cs_status codes; argument errors enqueue
+ *     nothing.  A launch failure reports CS_ERR_HIP; an earlier asynchronous fault is
+ *     reported by whichever call observes it.  No C++ exception crosses the ABI.
+ *   - Interval counts are exact integers: bit-exact results for the causal matrix and N_n.
+ *   - n is limited to 2 <= n < 2^31 (CS_ERR_OVERFLOW above); memory bounds it earlier:
+ *     the matrix takes n * cs_ld_words(n) * 8 bytes (2 GiB at n = 131072).
+ */
+#ifndef CAUSAL_H
+#define CAUSAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CS_OK = 0,
+    CS_ERR_INVALID_ARG = 1,  /* null pointer, n < 2, bad eps, ld too small ...        */
+    CS_ERR_UNSUPPORTED = 2,  /* unknown region / counter / dimension                   */
+    CS_ERR_WORKSPACE = 3,    /* workspace smaller than the matching *_workspace_bytes */
+    CS_ERR_OVERFLOW = 4,     /* n >= 2^31, or a size that would overflow              */
+    CS_ERR_HIP = 5,          /* a HIP runtime call or kernel launch failed            */
+    CS_ERR_NO_DEVICE = 6     /* no gfx950 device is visible                           */
+} cs_status;
+
+/* Regions (App. A).  Coordinates are stored as SoA planes: coords[p * n + i].
+ *   CS_MINK2_DIAMOND  1+1 Minkowski causal diamond in light-cone coordinates,
+ *                     (u, v) uniform in [0,1)^2.  Planes: u, v.
+ *                     i ≺ j  iff  u_i < u_j and v_i < v_j.
+ *   CS_MINK4_DIAMOND  3+1 Minkowski Alexandrov interval of height 1 between (0,0) and
+ *                     (1,0): uniform by rejection from [0,1) x [-1/2,1/2)^3.
+ *                     Planes: t, x, y, z.  i ≺ j iff dt > 0 and dt^2 > (dx^2+dy^2)+dz^2.
+ *   CS_DS4_SLAB       3+1 de Sitter slab, spherical foliation, conformal time
+ *                     eta in [-eta0, eta0] with density ∝ sec^4(eta), uniform on S^3.
+ *                     Planes: tan(eta), cos(eta), sin(eta), n0, n1, n2, n3 (unit vector).
+ *                     i ≺ j iff eta_i < eta_j and cos(eta_j - eta_i) < n_i . n_j.
+ * Relations are strict: null-separated and equal-time pairs are unrelated.  All
+ * predicates are evaluated in IEEE fp64 in the order written, without contraction. */
+enum { CS_MINK2_DIAMOND = 0, CS_MINK4_DIAMOND = 1, CS_DS4_SLAB = 2 };
+
+/* Interval counters. */
+enum {
+    CS_COUNT_BITSET = 0,  /* VALU: 32-bit AND + popcount over LDS-staged row words     */
+    CS_COUNT_MFMA = 1     /* dense C.C on int8 MFMA (v_mfma_i32_32x32x32_i8), int32 acc */
+};
+
+/* Number of fp64 coordinate planes of a region (2, 4 or 7); -1 if unknown. */
+int cs_coord_planes(int region);
+
+/* Row stride of the packed matrix in uint64 words: n rounded up to 512 bits. */
+int64_t cs_ld_words(int64_t n);
+
+/* Human-readable name of a status code (static string). */
+const char *cs_status_string(cs_status s);
+
+/* Device workspace needed by cs_sprinkle for (region, n), in bytes. */
+size_t cs_sprinkle_workspace_bytes(int region, int64_t n);
+
+/*
+ * Sprinkle n points into `region` from `seed` and store them time-ordered.
+ *   eta0       half-width of the de Sitter slab in conformal time, 0 < eta0 < pi/2
+ *              (ignored for the Minkowski diamonds).
+ *   seed       64-bit seed of the counter-based generator (SplitMix64 outputs).
+ *   coords     device, cs_coord_planes(region) * n doubles, written as SoA planes.
+ *   workspace  device, at least cs_sprinkle_workspace_bytes(region, n) bytes.
+ * Order: 1+1 by the exact integer (u + v) * 2^53, 3+1 diamond by t, de Sitter by
+ * tan(eta); ties by generation index.  Every relation then has i < j.
+ * The 3+1 diamond keeps the first n accepted candidates in candidate order.
+ */
+cs_status cs_sprinkle(int region, double eta0, uint64_t seed, int64_t n, double *coords,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Causal matrix S = C + C^T of n time-ordered points (C strictly upper triangular).
+ *   coords  device, SoA planes as written by cs_sprinkle (any time-ordered input works).
+ *   bits    device, n * ld_words uint64.  Bit j of row i is bit (j & 63) of word
+ *           bits[i * ld_words + (j >> 6)].  Every word is written, padding bits as 0.
+ *   ld_words >= cs_ld_words(n) (CS_ERR_INVALID_ARG otherwise).
+ */
+cs_status cs_causal_matrix(int region, const double *coords, int64_t n, uint64_t *bits,
+                           int64_t ld_words, void *stream);
+
+/* Device workspace needed by cs_interval_histogram, in bytes. */
+size_t cs_histogram_workspace_bytes(int64_t n, int counter);
+
+/*
+ * Interval abundances: hist[m] = N_m = number of pairs i < j with i ≺ j and exactly m
+ * elements k with i ≺ k ≺ j, for m = 0 .. n-2 (the thesis's n_{m+1}).
+ *   bits     device, the matrix from cs_causal_matrix (n rows, ld_words stride).
+ *   counter  CS_COUNT_BITSET or CS_COUNT_MFMA; both give identical results.
+ *   hist     device, n-1 uint64, overwritten (zeroed by the callee).
+ *   workspace device, at least cs_histogram_workspace_bytes(n, counter) bytes.
+ */
+cs_status cs_interval_histogram(const uint64_t *bits, int64_t n, int64_t ld_words, int counter,
+                                uint64_t *hist, void *workspace, size_t workspace_bytes,
+                                void *stream);
+
+/*
+ * Benincasa-Dowker action from the abundances (l = l_p).
+ *   dim = 2: eps == 0: S = 2 (N - 2N_0 + 4N_1 - 2N_2)
+ *            eps > 0 : S = 2 eps [N - 2 eps sum_m N_m f_2(m, eps)]
+ *   dim = 4: eps == 0: S = (4/sqrt 6)(N - N_0 + 9N_1 - 16N_2 + 8N_3)
+ *            eps > 0 : S = 4 sqrt(eps/6) [N - eps sum_m N_m f_4(m, eps)]
+ *   0 <= eps <= 1; at eps = 1 the smeared form equals the local one.
+ *   hist  device, n-1 uint64.   out  device, one double.
+ * The local combination is an exact int64; the smeared sum is accumulated in
+ * double-double (weights included), then rounded once to fp64.
+ */
+cs_status cs_action(const uint64_t *hist, int64_t n, int dim, double eps, double *out,
+                    void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * Ensembles: `count` independent 1+1 diamonds of sizes n[k] (2 <= n[k] <= 8192).
+ * cs_batch_plan builds a host-side plan (sizes, offsets, work list, tile choice).
+ * cs_batch_run enqueues the whole pipeline -- sprinkle, matrix, counts, actions --
+ * as a fixed sequence of kernels with no host synchronisation and no allocation, so
+ * the caller may capture it in a HIP graph.
+ *   seeds      device, count uint64.
+ *   workspace  device, cs_batch_workspace_bytes(plan) bytes.
+ *   hist       device, cs_batch_hist_len(plan) uint64: instance k's N_m at
+ *              hist[cs_batch_hist_offset(plan, k) + m], m = 0 .. n[k]-2.
+ *   actions    device, count * n_eps doubles: actions[k * n_eps + e] for eps[e]
+ *              (eps[e] == 0 selects the local action).
+ * --------------------------------------------------------------------------------- */
+typedef struct cs_batch_plan_t *cs_batch_plan_handle;
+
+cs_status cs_batch_plan(int64_t count, const int64_t *n /* host */, int counter,
+                        int n_eps, const double *eps /* host */, cs_batch_plan_handle *plan);
+size_t cs_batch_workspace_bytes(cs_batch_plan_handle plan);
+int64_t cs_batch_hist_len(cs_batch_plan_handle plan);
+int64_t cs_batch_hist_offset(cs_batch_plan_handle plan, int64_t k);
+cs_status cs_batch_run(cs_batch_plan_handle plan, const uint64_t *seeds, uint64_t *hist,
+                       double *actions, void *workspace, size_t workspace_bytes, void *stream);
+cs_status cs_batch_free(cs_batch_plan_handle plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAUSAL_H */

@@ -60,10 +60,14 @@ def lib():
         L.or_ld_words.restype = i64
         L.or_causal_matrix.argtypes = [c_int, p, i64, p, i64]
         L.or_causal_matrix.restype = c_int
+        L.or_causal_rows.argtypes = [c_int, p, i64, p, i64, p, i64]
+        L.or_causal_rows.restype = c_int
         L.or_histogram_naive.argtypes = [p, i64, i64, p]
         L.or_histogram_naive.restype = c_int
         L.or_histogram_fast.argtypes = [p, i64, i64, p, i64, i64]
         L.or_histogram_fast.restype = i64
+        L.or_histogram_fast_rows.argtypes = [p, i64, i64, p, p, i64]
+        L.or_histogram_fast_rows.restype = i64
         L.or_pair_interval.argtypes = [p, i64, i64, i64]
         L.or_pair_interval.restype = i64
         L.or_degrees.argtypes = [p, i64, i64, p, p, ctypes.POINTER(u64), ctypes.POINTER(u64)]
@@ -116,6 +120,18 @@ def causal_matrix(region: int, coords: np.ndarray, ld: int | None = None) -> np.
     return bits
 
 
+def causal_rows(region: int, coords: np.ndarray, rows, ld: int | None = None) -> np.ndarray:
+    """Rows `rows` of the symmetric packed causal matrix, uint64 array (len(rows), ld)."""
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    n = coords.shape[1]
+    ld = ld_words(n) if ld is None else ld
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.zeros((len(rows), ld), dtype=np.uint64)
+    if lib().or_causal_rows(region, _ptr(coords), n, _ptr(rows), len(rows), _ptr(out), ld) != 0:
+        raise ValueError("or_causal_rows failed")
+    return out
+
+
 def histogram_naive(bits: np.ndarray, n: int) -> np.ndarray:
     bits = np.ascontiguousarray(bits, dtype=np.uint64)
     hist = np.zeros(max(n - 1, 1), dtype=np.uint64)
@@ -132,6 +148,18 @@ def histogram_fast(bits: np.ndarray, n: int, row_begin: int = 0, row_end: int | 
     pairs = lib().or_histogram_fast(_ptr(bits), n, bits.shape[1], _ptr(hist), row_begin, row_end)
     if pairs < 0:
         raise ValueError("or_histogram_fast failed")
+    return hist, pairs
+
+
+def histogram_fast_rows(bits: np.ndarray, n: int, rows):
+    """Fast tier over the listed rows only; returns (hist, pairs_counted)."""
+    bits = np.ascontiguousarray(bits, dtype=np.uint64)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    hist = np.zeros(max(n - 1, 1), dtype=np.uint64)
+    pairs = lib().or_histogram_fast_rows(_ptr(bits), n, bits.shape[1], _ptr(hist), _ptr(rows),
+                                         len(rows))
+    if pairs < 0:
+        raise ValueError("or_histogram_fast_rows failed")
     return hist, pairs
 
 

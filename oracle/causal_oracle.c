@@ -191,16 +191,22 @@ int or_sprinkle(int region, double eta0, uint64_t seed, int64_t n, double *coord
             double c = 1.0 / sqrt(1.0 + x * x);
             double sn_eta = x * c;
             uint64_t ps = or_output(sn, (uint64_t)g);  /* per-point generator state */
-            double a[4], r2;
-            uint64_t k = 0;
-            for (;;) {
+            /* Try k draws 4k..4k+3 as a point of [-1,1)^4; keep the first one inside
+             * the unit ball (and not at its centre).  After 4096 failures (probability
+             * 0.69^4096) the direction (1,0,0,0) is used so the loop is bounded. */
+            double a[4] = {1.0, 0.0, 0.0, 0.0}, r2 = 1.0;
+            for (uint64_t k = 0; k < 4096; k++) {
+                double b[4];
                 for (int q = 0; q < 4; q++)
-                    a[q] = 2.0 * or_unit(or_output(ps, 4 * k + (uint64_t)q)) - 1.0;
-                r2 = a[0] * a[0] + a[1] * a[1];
-                r2 = r2 + a[2] * a[2];
-                r2 = r2 + a[3] * a[3];
-                k++;
-                if (r2 < 1.0 && r2 > 0x1.0p-40) break;
+                    b[q] = 2.0 * or_unit(or_output(ps, 4 * k + (uint64_t)q)) - 1.0;
+                double s2 = b[0] * b[0] + b[1] * b[1];
+                s2 = s2 + b[2] * b[2];
+                s2 = s2 + b[3] * b[3];
+                if (s2 < 1.0 && s2 > 0x1.0p-40) {
+                    for (int q = 0; q < 4; q++) a[q] = b[q];
+                    r2 = s2;
+                    break;
+                }
             }
             double r = sqrt(r2);
             raw[0 * n + g] = x;
@@ -268,6 +274,26 @@ int or_causal_matrix(int region, const double *coords, int64_t n, uint64_t *bits
             int r = i < j ? or_related(region, coords, n, i, j)
                           : or_related(region, coords, n, j, i);
             if (r) row[j >> 6] |= 1ULL << (j & 63);
+        }
+    }
+    return 0;
+}
+
+/* Selected rows of the same matrix: out[r*ld ...] is row rows[r]. */
+int or_causal_rows(int region, const double *coords, int64_t n, const int64_t *rows,
+                   int64_t nrows, uint64_t *out, int64_t ld)
+{
+    if (or_coord_planes(region) < 0 || n < 1 || ld * 64 < n) return -1;
+    memset(out, 0, sizeof(uint64_t) * (size_t)nrows * (size_t)ld);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < nrows; r++) {
+        int64_t i = rows[r];
+        uint64_t *row = out + r * ld;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            int rel = i < j ? or_related(region, coords, n, i, j)
+                            : or_related(region, coords, n, j, i);
+            if (rel) row[j >> 6] |= 1ULL << (j & 63);
         }
     }
     return 0;
@@ -342,6 +368,33 @@ int64_t or_histogram_fast(const uint64_t *bits, int64_t n, int64_t ld, uint64_t 
         uint64_t *mine = (uint64_t *)calloc((size_t)nb, sizeof(uint64_t));
 #pragma omp for schedule(dynamic, 1)
         for (int64_t i = row_begin; i < row_end; i++) {
+            for (int64_t j = i + 1; j < n; j++) {
+                if (!or_bit(bits, ld, i, j)) continue;
+                mine[or_pair_interval(bits, ld, i, j)]++;
+                pairs++;
+            }
+        }
+#pragma omp critical
+        for (int64_t m = 0; m < nb; m++) hist[m] += mine[m];
+        free(mine);
+    }
+    return pairs;
+}
+
+/* The same tier over an arbitrary list of rows i (all j > i): a bounded sample of
+ * the full count, used to time the CPU.  Returns the pairs counted. */
+int64_t or_histogram_fast_rows(const uint64_t *bits, int64_t n, int64_t ld, uint64_t *hist,
+                               const int64_t *rows, int64_t nrows)
+{
+    if (n < 2) return -1;
+    int64_t nb = n - 1, pairs = 0;
+    memset(hist, 0, sizeof(uint64_t) * (size_t)nb);
+#pragma omp parallel reduction(+ : pairs)
+    {
+        uint64_t *mine = (uint64_t *)calloc((size_t)nb, sizeof(uint64_t));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t r = 0; r < nrows; r++) {
+            int64_t i = rows[r];
             for (int64_t j = i + 1; j < n; j++) {
                 if (!or_bit(bits, ld, i, j)) continue;
                 mine[or_pair_interval(bits, ld, i, j)]++;

@@ -1,0 +1,187 @@
+"""Thin ctypes binding of libcausal.so (declared in include/causal.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.  Functions
+carry the C entry points' names.  Device buffers are torch tensors on the current
+ROCm device; work is enqueued on ``torch.cuda.current_stream()`` unless a stream is
+given.  The library must have been built (``paper_1805_04463_amd.build.build()``);
+there is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libcausal.so")
+
+CS_MINK2_DIAMOND, CS_MINK4_DIAMOND, CS_DS4_SLAB = 0, 1, 2
+CS_COUNT_BITSET, CS_COUNT_MFMA = 0, 1
+REGION_DIM = {CS_MINK2_DIAMOND: 2, CS_MINK4_DIAMOND: 4, CS_DS4_SLAB: 4}
+
+SYMBOLS = [
+    "cs_coord_planes", "cs_ld_words", "cs_status_string", "cs_sprinkle_workspace_bytes",
+    "cs_sprinkle", "cs_causal_matrix", "cs_histogram_workspace_bytes", "cs_interval_histogram",
+    "cs_action", "cs_batch_plan", "cs_batch_workspace_bytes", "cs_batch_hist_len",
+    "cs_batch_hist_offset", "cs_batch_run", "cs_batch_free",
+]
+
+
+class CausalError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CausalError(f"{LIB_PATH} is missing: run paper_1805_04463_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, u64, dbl, c_int, p, sz = (ctypes.c_int64, ctypes.c_uint64, ctypes.c_double,
+                                       ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t)
+        sig = {
+            "cs_coord_planes": (c_int, [c_int]),
+            "cs_ld_words": (i64, [i64]),
+            "cs_status_string": (ctypes.c_char_p, [c_int]),
+            "cs_sprinkle_workspace_bytes": (sz, [c_int, i64]),
+            "cs_sprinkle": (c_int, [c_int, dbl, u64, i64, p, p, sz, p]),
+            "cs_causal_matrix": (c_int, [c_int, p, i64, p, i64, p]),
+            "cs_histogram_workspace_bytes": (sz, [i64, c_int]),
+            "cs_interval_histogram": (c_int, [p, i64, i64, c_int, p, p, sz, p]),
+            "cs_action": (c_int, [p, i64, c_int, dbl, p, p]),
+            "cs_batch_plan": (c_int, [i64, p, c_int, c_int, p, ctypes.POINTER(p)]),
+            "cs_batch_workspace_bytes": (sz, [p]),
+            "cs_batch_hist_len": (i64, [p]),
+            "cs_batch_hist_offset": (i64, [p, i64]),
+            "cs_batch_run": (c_int, [p, p, p, p, p, sz, p]),
+            "cs_batch_free": (c_int, [p]),
+        }
+        for name, (res, args) in sig.items():
+            if hasattr(L, name):
+                f = getattr(L, name)
+                f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().cs_status_string(rc).decode()
+        raise CausalError(f"{what}: {msg} (status {rc})")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        raise CausalError("no ROCm GPU visible to torch")
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    if not t.is_cuda:
+        raise CausalError("expected a device tensor")
+    if not t.is_contiguous():
+        raise CausalError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _u8_workspace(nbytes: int) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=_dev())
+
+
+def cs_coord_planes(region: int) -> int:
+    return lib().cs_coord_planes(region)
+
+
+def cs_ld_words(n: int) -> int:
+    return lib().cs_ld_words(n)
+
+
+def cs_sprinkle(region: int, n: int, seed: int, eta0: float = 1.2, stream=None) -> torch.Tensor:
+    """Time-ordered coordinates, float64 device tensor (planes, n)."""
+    planes = lib().cs_coord_planes(region)
+    if planes < 0:
+        raise CausalError(f"unknown region {region}")
+    coords = torch.empty((planes, n), dtype=torch.float64, device=_dev())
+    ws_bytes = lib().cs_sprinkle_workspace_bytes(region, n)
+    ws = _u8_workspace(ws_bytes)
+    _check(lib().cs_sprinkle(region, eta0, seed & (2**64 - 1), n, _ptr(coords), _ptr(ws), ws_bytes,
+                             _stream(stream)), "cs_sprinkle")
+    coords._cs_keepalive = ws  # workspace must outlive the enqueued kernels
+    return coords
+
+
+def cs_causal_matrix(region: int, coords: torch.Tensor, n: int | None = None,
+                     ld_words: int | None = None, out: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+    """Symmetric packed matrix as an int64 device tensor (n, ld) holding uint64 words."""
+    n = coords.shape[1] if n is None else n
+    ld = lib().cs_ld_words(n) if ld_words is None else ld_words
+    bits = out if out is not None else torch.empty((n, ld), dtype=torch.int64, device=_dev())
+    if coords.dtype != torch.float64:
+        raise CausalError("coords must be float64")
+    _check(lib().cs_causal_matrix(region, _ptr(coords), n, _ptr(bits), ld, _stream(stream)),
+           "cs_causal_matrix")
+    return bits
+
+
+def cs_interval_histogram(bits: torch.Tensor, n: int, counter: int = CS_COUNT_MFMA,
+                          out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                          stream=None) -> torch.Tensor:
+    """N_m for m = 0..n-2 as an int64 device tensor (uint64 counts)."""
+    ld = bits.shape[1]
+    hist = out if out is not None else torch.empty(n - 1, dtype=torch.int64, device=_dev())
+    ws_bytes = lib().cs_histogram_workspace_bytes(n, counter)
+    ws = workspace if workspace is not None else _u8_workspace(ws_bytes)
+    _check(lib().cs_interval_histogram(_ptr(bits), n, ld, counter, _ptr(hist), _ptr(ws),
+                                       ws.numel(), _stream(stream)), "cs_interval_histogram")
+    hist._cs_keepalive = ws
+    return hist
+
+
+def cs_action(hist: torch.Tensor, n: int, dim: int, eps: float = 0.0,
+              out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """The action as a one-element float64 device tensor."""
+    o = out if out is not None else torch.empty(1, dtype=torch.float64, device=_dev())
+    _check(lib().cs_action(_ptr(hist), n, dim, float(eps), _ptr(o), _stream(stream)), "cs_action")
+    return o
+
+
+class BatchPlan:
+    """Host-side plan of an ensemble of 1+1 diamonds (wraps cs_batch_plan)."""
+
+    def __init__(self, sizes, counter: int = CS_COUNT_MFMA, eps=(0.0,)):
+        import numpy as np
+        self.sizes = np.ascontiguousarray(sizes, dtype=np.int64)
+        self.eps = np.ascontiguousarray(eps, dtype=np.float64)
+        self.count = len(self.sizes)
+        h = ctypes.c_void_p()
+        _check(lib().cs_batch_plan(self.count, self.sizes.ctypes.data_as(ctypes.c_void_p), counter,
+                                   len(self.eps), self.eps.ctypes.data_as(ctypes.c_void_p),
+                                   ctypes.byref(h)), "cs_batch_plan")
+        self.handle = h
+        self.ws_bytes = lib().cs_batch_workspace_bytes(h)
+        self.hist_len = lib().cs_batch_hist_len(h)
+        self.offsets = [lib().cs_batch_hist_offset(h, k) for k in range(self.count)]
+
+    def run(self, seeds: torch.Tensor, hist: torch.Tensor, actions: torch.Tensor,
+            workspace: torch.Tensor, stream=None):
+        _check(lib().cs_batch_run(self.handle, _ptr(seeds), _ptr(hist), _ptr(actions),
+                                  _ptr(workspace), workspace.numel(), _stream(stream)),
+               "cs_batch_run")
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) is not None and self.handle.value:
+                lib().cs_batch_free(self.handle)
+        except Exception:
+            pass

@@ -1,0 +1,219 @@
+// Benincasa-Dowker action from the interval abundances (Sec. 4.2).
+//
+// Local:    S^(1+1) = 2 (N - 2N_0 + 4N_1 - 2N_2),
+//           S^(3+1) = (4/sqrt 6)(N - N_0 + 9N_1 - 16N_2 + 8N_3)      (l = l_p)
+// Smeared:  S_eps^(1+1) = 2 eps [N - 2 eps sum_m N_m f_2(m, eps)]
+//           S_eps^(3+1) = 4 sqrt(eps/6) [N - eps sum_m N_m f_4(m, eps)]
+// with the smearing functions multiplied out so no power of (1 - eps) is negative:
+//   f_2(m) = (1-e)^(m-2) [(1-e)^2 - 2m e(1-e) + m(m-1)/2 e^2]                m >= 2
+//   f_4(m) = (1-e)^(m-3) [(1-e)^3 - 9m e(1-e)^2 + 8m(m-1) e^2 (1-e)
+//                          - 4 (m(m-1)(m-2)/3) e^3]                          m >= 3
+// and the first terms written directly.  The smeared sum is badly conditioned (the
+// terms are far larger than the result), so weights and sum are carried in
+// double-double (error-free transformations: Knuth's two-sum, Dekker's product via
+// fma), then rounded once.  The local combination is an exact 128-bit integer.
+//
+// One workgroup of 1024 threads; thread t owns a contiguous range of bins and
+// advances (1-e)^(m-3) by one multiplication per bin.
+#include "common.h"
+
+namespace cs {
+namespace {
+
+struct dd {
+  double hi, lo;
+};
+
+__device__ inline dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  double e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+__device__ inline dd fast_two_sum(double a, double b) {  // |a| >= |b|
+  double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ inline dd two_prod(double a, double b) {
+  double p = a * b;
+  return {p, fma(a, b, -p)};
+}
+__device__ inline dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+__device__ inline dd dd_mul(dd a, dd b) {
+  dd p = two_prod(a.hi, b.hi);
+  p.lo += a.hi * b.lo + a.lo * b.hi;
+  return fast_two_sum(p.hi, p.lo);
+}
+__device__ inline dd dd_mul_d(dd a, double b) {
+  dd p = two_prod(a.hi, b);
+  p.lo += a.lo * b;
+  return fast_two_sum(p.hi, p.lo);
+}
+__device__ inline dd dd_from_u64(uint64_t x) {
+  double hi = (double)x;                       // rounded
+  int64_t rest = (int64_t)(x - (uint64_t)hi);  // exact remainder, |rest| < 2^11
+  return fast_two_sum(hi, (double)rest);
+}
+__device__ inline dd dd_powi(dd b, int64_t e) {  // e >= 0, 0^0 = 1
+  dd r = {1.0, 0.0};
+  while (e > 0) {
+    if (e & 1) r = dd_mul(r, b);
+    b = dd_mul(b, b);
+    e >>= 1;
+  }
+  return r;
+}
+__device__ inline dd dd_sqrt(dd a) {  // one Newton step from the fp64 root
+  if (a.hi <= 0.0) return {0.0, 0.0};
+  double s = sqrt(a.hi);
+  dd s2 = two_prod(s, s);
+  double corr = ((a.hi - s2.hi) - s2.lo + a.lo) / (2.0 * s);
+  return fast_two_sum(s, corr);
+}
+
+// Bracket polynomials: f(m) = (1-e)^(m-K) * B(m) for m >= K (K = 2 or 4's 3).
+struct Smear {
+  int dim;
+  dd e, q;              // eps and 1 - eps
+  dd p[4];              // e^k (1-e)^(K-k), k = 0..K
+};
+
+__device__ inline dd bracket(const Smear& s, int64_t m) {
+  const double md = (double)m, m1 = (double)(m - 1), m2 = (double)(m - 2);
+  if (s.dim == 2) {
+    // (1-e)^2 - 2m e(1-e) + (m(m-1)/2) e^2 ; m(m-1)/2 is an integer
+    dd c2 = (m % 2 == 0) ? two_prod(md * 0.5, m1) : two_prod(md, m1 * 0.5);
+    dd r = s.p[0];
+    r = dd_add(r, dd_mul_d(s.p[1], -2.0 * md));
+    r = dd_add(r, dd_mul(s.p[2], c2));
+    return r;
+  }
+  // (1-e)^3 - 9m e(1-e)^2 + 8m(m-1) e^2(1-e) - 4 (m(m-1)(m-2)/3) e^3
+  dd c2 = dd_mul_d(two_prod(md, m1), 8.0);
+  double a = md, b = m1, c = m2;  // divide the factor that is a multiple of 3
+  if (m % 3 == 0) a = md / 3.0; else if ((m - 1) % 3 == 0) b = m1 / 3.0; else c = m2 / 3.0;
+  dd c3 = dd_mul_d(dd_mul_d(two_prod(a, b), c), -4.0);
+  dd r = s.p[0];
+  r = dd_add(r, dd_mul_d(s.p[1], -9.0 * md));
+  r = dd_add(r, dd_mul(s.p[2], c2));
+  r = dd_add(r, dd_mul(s.p[3], c3));
+  return r;
+}
+
+// f(m) for the first bins (m < K), from sum_k c_k(m) e^k (1-e)^(m-k).
+__device__ inline dd small_weight(const Smear& s, int64_t m) {
+  if (m == 0) return {1.0, 0.0};
+  if (s.dim == 2) {  // m = 1: (1-e) - 2e
+    return dd_add(s.q, dd_mul_d(s.e, -2.0));
+  }
+  if (m == 1) return dd_add(s.q, dd_mul_d(s.e, -9.0));  // (1-e) - 9e
+  // m = 2: (1-e)^2 - 18 e(1-e) + 16 e^2
+  dd r = dd_mul(s.q, s.q);
+  r = dd_add(r, dd_mul_d(dd_mul(s.e, s.q), -18.0));
+  r = dd_add(r, dd_mul_d(dd_mul(s.e, s.e), 16.0));
+  return r;
+}
+
+constexpr int kActThreads = 1024;
+
+__global__ __launch_bounds__(kActThreads) void k_action(const uint64_t* __restrict__ hist, int64_t n,
+                                                        int dim, double eps, double* __restrict__ out) {
+  const int64_t nb = n - 1;
+  if (eps == 0.0) {
+    if (threadIdx.x == 0) {
+      __int128 h[4] = {0, 0, 0, 0};
+      for (int m = 0; m < 4 && m < nb; ++m) h[m] = (__int128)hist[m];
+      __int128 I;
+      if (dim == 2) {
+        I = (__int128)n - 2 * h[0] + 4 * h[1] - 2 * h[2];
+        out[0] = 2.0 * (double)I;
+      } else {
+        I = (__int128)n - h[0] + 9 * h[1] - 16 * h[2] + 8 * h[3];
+        // 4/sqrt(6) in double-double times I (I split exactly into two doubles)
+        dd c = dd_sqrt(dd{6.0, 0.0});
+        // 4 / c by one Newton step on the fp64 quotient
+        double q0 = 4.0 / c.hi;
+        dd qc = dd_mul_d(c, q0);
+        double corr = ((4.0 - qc.hi) - qc.lo) / c.hi;
+        dd k = fast_two_sum(q0, corr);
+        double Ihi = (double)I;
+        double Ilo = (double)(I - (__int128)Ihi);
+        dd r = dd_add(dd_mul_d(k, Ihi), dd_mul_d(k, Ilo));
+        out[0] = r.hi + r.lo;
+      }
+    }
+    return;
+  }
+  __shared__ double s_hi[kActThreads], s_lo[kActThreads];
+  Smear sm;
+  sm.dim = dim;
+  sm.e = {eps, 0.0};
+  sm.q = two_sum(1.0, -eps);
+  const int K = dim == 2 ? 2 : 3;
+  for (int k = 0; k <= K; ++k) sm.p[k] = dd_mul(dd_powi(sm.e, k), dd_powi(sm.q, K - k));
+
+  const int64_t per = ceil_div(nb, kActThreads);
+  const int64_t m0 = (int64_t)threadIdx.x * per;
+  const int64_t m1 = (m0 + per < nb ? m0 + per : nb);
+  dd acc = {0.0, 0.0};
+  int64_t m = m0;
+  for (; m < m1 && m < K; ++m) {
+    if (hist[m]) acc = dd_add(acc, dd_mul(dd_from_u64(hist[m]), small_weight(sm, m)));
+  }
+  if (m < m1) {
+    dd pw = dd_powi(sm.q, m - K);  // (1-e)^(m-K)
+    for (; m < m1; ++m) {
+      const uint64_t h = hist[m];
+      if (h) acc = dd_add(acc, dd_mul(dd_from_u64(h), dd_mul(pw, bracket(sm, m))));
+      pw = dd_mul(pw, sm.q);
+    }
+  }
+  s_hi[threadIdx.x] = acc.hi;
+  s_lo[threadIdx.x] = acc.lo;
+  __syncthreads();
+  for (int w = kActThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < (unsigned)w) {
+      dd a = {s_hi[threadIdx.x], s_lo[threadIdx.x]};
+      dd b = {s_hi[threadIdx.x + w], s_lo[threadIdx.x + w]};
+      a = dd_add(a, b);
+      s_hi[threadIdx.x] = a.hi;
+      s_lo[threadIdx.x] = a.lo;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    dd sum = {s_hi[0], s_lo[0]};
+    dd ec = dim == 2 ? dd{2.0 * eps, 0.0} : dd{eps, 0.0};
+    dd br = dd_add(dd{(double)n, 0.0}, dd_mul(dd{-ec.hi, -ec.lo}, sum));
+    dd pref;
+    if (dim == 2) {
+      pref = {2.0 * eps, 0.0};
+    } else {
+      // eps/6 in double-double (fp64 quotient plus its exact residual / 6), then sqrt
+      double q0 = eps / 6.0;
+      dd q6 = two_prod(q0, 6.0);
+      dd e6 = fast_two_sum(q0, ((eps - q6.hi) - q6.lo) / 6.0);
+      pref = dd_mul_d(dd_sqrt(e6), 4.0);
+    }
+    dd s = dd_mul(pref, br);
+    out[0] = s.hi + s.lo;
+  }
+}
+
+}  // namespace
+
+cs_status launch_action(const uint64_t* hist, int64_t n, int dim, double eps, double* out,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_action, dim3(1), dim3(kActThreads), 0, st, hist, n, dim, eps, out);
+  CS_LAUNCH_CHECK();
+  return CS_OK;
+}
+
+}  // namespace cs

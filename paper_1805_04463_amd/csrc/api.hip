@@ -1,0 +1,94 @@
+// extern "C" entry points of libcausal.so: argument validation, workspace checks,
+// then the internal launchers.  Declarations and the contract are in include/causal.h.
+#include <math.h>
+
+#include "common.h"
+
+using namespace cs;
+
+namespace {
+
+constexpr int64_t kMaxN = (int64_t)1 << 31;
+
+inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+cs_status check_n(int64_t n) {
+  if (n < 2) return CS_ERR_INVALID_ARG;
+  if (n >= kMaxN) return CS_ERR_OVERFLOW;
+  return CS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cs_coord_planes(int region) { return coord_planes(region); }
+
+int64_t cs_ld_words(int64_t n) { return n < 0 ? -1 : ld_words(n); }
+
+const char* cs_status_string(cs_status s) {
+  switch (s) {
+    case CS_OK: return "ok";
+    case CS_ERR_INVALID_ARG: return "invalid argument";
+    case CS_ERR_UNSUPPORTED: return "unsupported region, counter or dimension";
+    case CS_ERR_WORKSPACE: return "workspace too small";
+    case CS_ERR_OVERFLOW: return "size too large";
+    case CS_ERR_HIP: return "HIP runtime error";
+    case CS_ERR_NO_DEVICE: return "no gfx950 device";
+    default: return "unknown status";
+  }
+}
+
+size_t cs_sprinkle_workspace_bytes(int region, int64_t n) {
+  if (coord_planes(region) < 0 || check_n(n) != CS_OK) return 0;
+  return sprinkle_ws_bytes(region, n);
+}
+
+cs_status cs_sprinkle(int region, double eta0, uint64_t seed, int64_t n, double* coords,
+                      void* workspace, size_t workspace_bytes, void* stream) {
+  if (coord_planes(region) < 0) return CS_ERR_UNSUPPORTED;
+  cs_status s = check_n(n);
+  if (s != CS_OK) return s;
+  if (!coords || !workspace) return CS_ERR_INVALID_ARG;
+  if (region == CS_DS4_SLAB && !(eta0 > 0.0 && eta0 < 1.5707963267948966))
+    return CS_ERR_INVALID_ARG;
+  if (workspace_bytes < sprinkle_ws_bytes(region, n)) return CS_ERR_WORKSPACE;
+  return launch_sprinkle(region, eta0, seed, n, coords, workspace, as_stream(stream));
+}
+
+cs_status cs_causal_matrix(int region, const double* coords, int64_t n, uint64_t* bits,
+                           int64_t ld_words_, void* stream) {
+  if (coord_planes(region) < 0) return CS_ERR_UNSUPPORTED;
+  cs_status s = check_n(n);
+  if (s != CS_OK) return s;
+  if (!coords || !bits || ld_words_ < ld_words(n)) return CS_ERR_INVALID_ARG;
+  if (ceil_div(n, 64) > 65535) return CS_ERR_OVERFLOW;  // grid rows of 64-point blocks
+  return launch_causal_matrix(region, coords, n, bits, ld_words_, as_stream(stream));
+}
+
+size_t cs_histogram_workspace_bytes(int64_t n, int counter) {
+  if (check_n(n) != CS_OK || (counter != CS_COUNT_BITSET && counter != CS_COUNT_MFMA)) return 0;
+  return histogram_ws_bytes(n, counter);
+}
+
+cs_status cs_interval_histogram(const uint64_t* bits, int64_t n, int64_t ld_words_, int counter,
+                                uint64_t* hist, void* workspace, size_t workspace_bytes,
+                                void* stream) {
+  if (counter != CS_COUNT_BITSET && counter != CS_COUNT_MFMA) return CS_ERR_UNSUPPORTED;
+  cs_status s = check_n(n);
+  if (s != CS_OK) return s;
+  if (!bits || !hist || !workspace || ld_words_ < ld_words(n)) return CS_ERR_INVALID_ARG;
+  if (workspace_bytes < histogram_ws_bytes(n, counter)) return CS_ERR_WORKSPACE;
+  return launch_histogram(bits, n, ld_words_, counter, hist, workspace, as_stream(stream));
+}
+
+cs_status cs_action(const uint64_t* hist, int64_t n, int dim, double eps, double* out,
+                    void* stream) {
+  if (dim != 2 && dim != 4) return CS_ERR_UNSUPPORTED;
+  cs_status s = check_n(n);
+  if (s != CS_OK) return s;
+  if (!hist || !out || !(eps >= 0.0 && eps <= 1.0)) return CS_ERR_INVALID_ARG;
+  return launch_action(hist, n, dim, eps, out, as_stream(stream));
+}
+
+}  // extern "C"

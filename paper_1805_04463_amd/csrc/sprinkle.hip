@@ -1,0 +1,393 @@
+// Sprinkling and time ordering on the GPU (App. A "Causal Set Sprinklings";
+// Sec. 3.2 "Pairwise Relations": label elements so that no later index precedes
+// an earlier one).
+//
+// Pipeline per call: generate raw SoA coordinates + a 64-bit time key per point
+// -> bitonic sort of (key, generation index) pairs (LDS chunks of 2048 + global
+// merge steps) -> gather the coordinate planes into sorted order.
+// The 3+1 diamond is sampled by rejection: candidates are flagged, counted per
+// block, scanned, and the first n accepted are scattered in candidate order.
+#include "common.h"
+
+namespace cs {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kSortChunk = 2048;  // elements sorted per LDS pass (1024 threads)
+
+// Acceptance budget of the 3+1 rejection sampler: acceptance probability is the
+// diamond's volume pi/24 in the unit box; the budget covers the mean plus 12
+// standard deviations; a one-workgroup tail kernel handles any shortfall.
+int64_t mink4_candidates(int64_t n) {
+  const double p = 0.13089969389957471;  // pi / 24
+  double m = (double)n / p + 12.0 * sqrt((double)n * (1.0 - p)) / p + 4096.0;
+  return align_up((size_t)m, kBlock);
+}
+
+int64_t pow2_at_least(int64_t n) {
+  int64_t p = 2;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+struct SprinkleWs {
+  double* raw;
+  uint64_t* keys;
+  uint32_t* gens;
+  uint32_t* blk_count;   // 3+1 only
+  uint64_t* blk_offset;  // 3+1 only (exclusive scan), plus [nblk] = total
+};
+
+size_t layout(int region, int64_t n, void* base, SprinkleWs* w) {
+  const int planes = coord_planes(region);
+  const int64_t P = pow2_at_least(n);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  size_t o_raw = take(sizeof(double) * planes * n);
+  size_t o_keys = take(sizeof(uint64_t) * P);
+  size_t o_gens = take(sizeof(uint32_t) * P);
+  size_t o_cnt = 0, o_off = 0;
+  if (region == CS_MINK4_DIAMOND) {
+    int64_t nblk = mink4_candidates(n) / kBlock;
+    o_cnt = take(sizeof(uint32_t) * nblk);
+    o_off = take(sizeof(uint64_t) * (nblk + 1));
+  }
+  if (w) {
+    char* b = (char*)base;
+    w->raw = (double*)(b + o_raw);
+    w->keys = (uint64_t*)(b + o_keys);
+    w->gens = (uint32_t*)(b + o_gens);
+    w->blk_count = region == CS_MINK4_DIAMOND ? (uint32_t*)(b + o_cnt) : nullptr;
+    w->blk_offset = region == CS_MINK4_DIAMOND ? (uint64_t*)(b + o_off) : nullptr;
+  }
+  return off;
+}
+
+// ---------------------------------------------------------------------------
+// 1+1 diamond: u = U(2g), v = U(2g+1); key = exact integer (u + v) * 2^53.
+// ---------------------------------------------------------------------------
+__global__ void k_sprinkle_mink2(uint64_t skey, int64_t n, int64_t P, double* __restrict__ raw,
+                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ gens) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= P) return;
+  if (g < n) {
+    uint64_t ku = sm_output(skey, 2 * (uint64_t)g) >> 11;
+    uint64_t kv = sm_output(skey, 2 * (uint64_t)g + 1) >> 11;
+    raw[g] = (double)ku * 0x1.0p-53;
+    raw[n + g] = (double)kv * 0x1.0p-53;
+    keys[g] = ku + kv;
+    gens[g] = (uint32_t)g;
+  } else {
+    keys[g] = ~0ull;
+    gens[g] = 0xFFFFFFFFu;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3+1 diamond of height 1 by rejection from [0,1) x [-1/2,1/2)^3.
+// ---------------------------------------------------------------------------
+struct Cand4 {
+  double t, x, y, z;
+  uint64_t kt;
+  bool ok;
+};
+
+__device__ inline Cand4 mink4_candidate(uint64_t skey, uint64_t c) {
+  Cand4 r;
+  r.kt = sm_output(skey, 4 * c) >> 11;
+  r.t = (double)r.kt * 0x1.0p-53;
+  r.x = unit53(sm_output(skey, 4 * c + 1)) - 0.5;
+  r.y = unit53(sm_output(skey, 4 * c + 2)) - 0.5;
+  r.z = unit53(sm_output(skey, 4 * c + 3)) - 0.5;
+  double one_t = 1.0 - r.t;
+  double rad = r.t < one_t ? r.t : one_t;
+  double rr = __dadd_rn(__dmul_rn(r.x, r.x), __dmul_rn(r.y, r.y));
+  rr = __dadd_rn(rr, __dmul_rn(r.z, r.z));
+  r.ok = rr < __dmul_rn(rad, rad);
+  return r;
+}
+
+// Block-wide exclusive rank of `flag` among the block's threads, and the block total.
+__device__ inline uint32_t block_rank(bool flag, uint32_t* total, uint32_t* s_wave) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint64_t m = __ballot(flag);
+  uint32_t below = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) s_wave[wave] = (uint32_t)__popcll(m);
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    if (w < wave) base += s_wave[w];
+    tot += s_wave[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + below;
+}
+
+__global__ void k_mink4_count(uint64_t skey, uint32_t* __restrict__ blk_count) {
+  __shared__ uint32_t s_wave[kBlock / 64];
+  uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  Cand4 r = mink4_candidate(skey, c);
+  uint32_t tot;
+  block_rank(r.ok, &tot, s_wave);
+  if (threadIdx.x == 0) blk_count[blockIdx.x] = tot;
+}
+
+// Exclusive scan of nblk block counts by one workgroup of 1024 threads.
+__global__ void k_scan_counts(const uint32_t* __restrict__ cnt, int64_t nblk,
+                              uint64_t* __restrict__ off) {
+  __shared__ uint64_t s[1024];
+  uint64_t carry = 0;
+  for (int64_t base = 0; base < nblk; base += 1024) {
+    int64_t i = base + threadIdx.x;
+    uint64_t v = i < nblk ? cnt[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {  // Hillis-Steele inclusive scan
+      uint64_t a = threadIdx.x >= (unsigned)d ? s[threadIdx.x - d] : 0;
+      __syncthreads();
+      s[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (i < nblk) off[i] = carry + s[threadIdx.x] - v;
+    carry += s[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) off[nblk] = carry;
+}
+
+__device__ inline void put4(const Cand4& r, uint64_t rank, int64_t n, double* raw, uint64_t* keys,
+                            uint32_t* gens) {
+  raw[rank] = r.t;
+  raw[n + rank] = r.x;
+  raw[2 * n + rank] = r.y;
+  raw[3 * n + rank] = r.z;
+  keys[rank] = r.kt;
+  gens[rank] = (uint32_t)rank;
+}
+
+__global__ void k_mink4_scatter(uint64_t skey, int64_t n, const uint64_t* __restrict__ blk_off,
+                                double* __restrict__ raw, uint64_t* __restrict__ keys,
+                                uint32_t* __restrict__ gens) {
+  __shared__ uint32_t s_wave[kBlock / 64];
+  uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  Cand4 r = mink4_candidate(skey, c);
+  uint32_t tot;
+  uint32_t local = block_rank(r.ok, &tot, s_wave);
+  uint64_t rank = blk_off[blockIdx.x] + local;
+  if (r.ok && rank < (uint64_t)n) put4(r, rank, n, raw, keys, gens);
+}
+
+// Continues candidates after the budget if (improbably) fewer than n were accepted.
+// One workgroup; bounded number of rounds.
+__global__ void k_mink4_tail(uint64_t skey, int64_t n, int64_t M, const uint64_t* __restrict__ total,
+                             double* __restrict__ raw, uint64_t* __restrict__ keys,
+                             uint32_t* __restrict__ gens) {
+  __shared__ uint32_t s_wave[kBlock / 64];
+  uint64_t have = *total;
+  const int64_t kMaxRounds = 1ll << 22;
+  for (int64_t round = 0; have < (uint64_t)n && round < kMaxRounds; ++round) {
+    uint64_t c = (uint64_t)M + (uint64_t)round * kBlock + threadIdx.x;
+    Cand4 r = mink4_candidate(skey, c);
+    uint32_t tot;
+    uint32_t local = block_rank(r.ok, &tot, s_wave);
+    uint64_t rank = have + local;
+    if (r.ok && rank < (uint64_t)n) put4(r, rank, n, raw, keys, gens);
+    have += tot;
+  }
+}
+
+__global__ void k_pad_keys(int64_t n, int64_t P, uint64_t* __restrict__ keys,
+                           uint32_t* __restrict__ gens) {
+  int64_t g = n + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < P) {
+    keys[g] = ~0ull;
+    gens[g] = 0xFFFFFFFFu;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3+1 de Sitter slab: x = tan(eta) from the inverse CDF of (1 + x^2) dx,
+// x = 2 sinh(asinh(3y/2)/3); direction on S^3 by cube rejection, normalised.
+// ---------------------------------------------------------------------------
+__global__ void k_sprinkle_ds4(uint64_t skey_t, uint64_t skey_s, double X, int64_t n, int64_t P,
+                               double* __restrict__ raw, uint64_t* __restrict__ keys,
+                               uint32_t* __restrict__ gens) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= P) return;
+  if (g >= n) {
+    keys[g] = ~0ull;
+    gens[g] = 0xFFFFFFFFu;
+    return;
+  }
+  double Y = __dadd_rn(X, __ddiv_rn(__dmul_rn(__dmul_rn(X, X), X), 3.0));
+  double u = unit53(sm_output(skey_t, (uint64_t)g));
+  double y = __dmul_rn(__dsub_rn(__dmul_rn(2.0, u), 1.0), Y);
+  double x = __dmul_rn(2.0, sinh(__ddiv_rn(asinh(__dmul_rn(1.5, y)), 3.0)));
+  double ce = __ddiv_rn(1.0, __dsqrt_rn(__dadd_rn(1.0, __dmul_rn(x, x))));
+  double se = __dmul_rn(x, ce);
+  uint64_t ps = sm_output(skey_s, (uint64_t)g);
+  double a0 = 1.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, r2 = 1.0;
+  for (int k = 0; k < kSphereTries; ++k) {
+    double b0 = __dsub_rn(__dmul_rn(2.0, unit53(sm_output(ps, 4 * (uint64_t)k + 0))), 1.0);
+    double b1 = __dsub_rn(__dmul_rn(2.0, unit53(sm_output(ps, 4 * (uint64_t)k + 1))), 1.0);
+    double b2 = __dsub_rn(__dmul_rn(2.0, unit53(sm_output(ps, 4 * (uint64_t)k + 2))), 1.0);
+    double b3 = __dsub_rn(__dmul_rn(2.0, unit53(sm_output(ps, 4 * (uint64_t)k + 3))), 1.0);
+    double q = __dadd_rn(__dmul_rn(b0, b0), __dmul_rn(b1, b1));
+    q = __dadd_rn(q, __dmul_rn(b2, b2));
+    q = __dadd_rn(q, __dmul_rn(b3, b3));
+    if (q < 1.0 && q > 0x1.0p-40) {
+      a0 = b0; a1 = b1; a2 = b2; a3 = b3; r2 = q;
+      break;
+    }
+  }
+  double r = __dsqrt_rn(r2);
+  raw[g] = x;
+  raw[n + g] = ce;
+  raw[2 * n + g] = se;
+  raw[3 * n + g] = __ddiv_rn(a0, r);
+  raw[4 * n + g] = __ddiv_rn(a1, r);
+  raw[5 * n + g] = __ddiv_rn(a2, r);
+  raw[6 * n + g] = __ddiv_rn(a3, r);
+  keys[g] = order_bits(x);
+  gens[g] = (uint32_t)g;
+}
+
+// ---------------------------------------------------------------------------
+// Bitonic sort of (key, gen) pairs, P a power of two.
+// ---------------------------------------------------------------------------
+__device__ inline void cmp_swap_lds(uint64_t* sk, uint32_t* sg, int i, int l, bool asc) {
+  uint64_t ka = sk[i], kb = sk[l];
+  uint32_t ga = sg[i], gb = sg[l];
+  bool gt = key_less(kb, gb, ka, ga);  // a > b
+  if (gt == asc) {
+    sk[i] = kb; sk[l] = ka;
+    sg[i] = gb; sg[l] = ga;
+  }
+}
+
+// kfirst == 0: full sort of each chunk (k = 2 .. CH).  Otherwise: the j < CH steps of
+// merge stage k = kfirst.  One thread per pair; CH/2 threads per block.
+__global__ void k_bitonic_lds(uint64_t* __restrict__ keys, uint32_t* __restrict__ gens, int CH,
+                              int64_t kfirst) {
+  __shared__ uint64_t sk[kSortChunk];
+  __shared__ uint32_t sg[kSortChunk];
+  const int64_t base = (int64_t)blockIdx.x * CH;
+  const int t = threadIdx.x;
+  sk[t] = keys[base + t];
+  sg[t] = gens[base + t];
+  sk[t + CH / 2] = keys[base + t + CH / 2];
+  sg[t + CH / 2] = gens[base + t + CH / 2];
+  int64_t k0 = kfirst ? kfirst : 2;
+  int64_t k1 = kfirst ? kfirst : CH;
+  for (int64_t k = k0; k <= k1; k <<= 1) {
+    int jstart = (int)((k >> 1) < (CH >> 1) ? (k >> 1) : (CH >> 1));
+    for (int j = jstart; j > 0; j >>= 1) {
+      __syncthreads();
+      int i = 2 * t - (t & (j - 1));
+      bool asc = ((base + i) & k) == 0;
+      cmp_swap_lds(sk, sg, i, i + j, asc);
+    }
+  }
+  __syncthreads();
+  keys[base + t] = sk[t];
+  gens[base + t] = sg[t];
+  keys[base + t + CH / 2] = sk[t + CH / 2];
+  gens[base + t + CH / 2] = sg[t + CH / 2];
+}
+
+__global__ void k_bitonic_global(uint64_t* __restrict__ keys, uint32_t* __restrict__ gens,
+                                 int64_t P, int64_t k, int64_t j) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P / 2) return;
+  int64_t i = 2 * t - (t & (j - 1));
+  int64_t l = i + j;
+  bool asc = (i & k) == 0;
+  uint64_t ka = keys[i], kb = keys[l];
+  uint32_t ga = gens[i], gb = gens[l];
+  if (key_less(kb, gb, ka, ga) == asc) {
+    keys[i] = kb; keys[l] = ka;
+    gens[i] = gb; gens[l] = ga;
+  }
+}
+
+__global__ void k_gather(const double* __restrict__ raw, const uint32_t* __restrict__ gens,
+                         int planes, int64_t n, double* __restrict__ coords) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t g = gens[i];
+  for (int p = 0; p < planes; ++p) coords[(int64_t)p * n + i] = raw[(int64_t)p * n + g];
+}
+
+cs_status bitonic_sort(uint64_t* keys, uint32_t* gens, int64_t P, hipStream_t st) {
+  const int CH = (int)(P < kSortChunk ? P : kSortChunk);
+  const unsigned nchunks = (unsigned)(P / CH);
+  hipLaunchKernelGGL(k_bitonic_lds, dim3(nchunks), dim3(CH / 2), 0, st, keys, gens, CH,
+                     (int64_t)0);
+  CS_LAUNCH_CHECK();
+  for (int64_t k = 2 * (int64_t)CH; k <= P; k <<= 1) {
+    for (int64_t j = k >> 1; j >= CH; j >>= 1) {
+      unsigned blocks = (unsigned)ceil_div(P / 2, 256);
+      hipLaunchKernelGGL(k_bitonic_global, dim3(blocks), dim3(256), 0, st, keys, gens, P, k, j);
+      CS_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_bitonic_lds, dim3(nchunks), dim3(CH / 2), 0, st, keys, gens, CH, k);
+    CS_LAUNCH_CHECK();
+  }
+  return CS_OK;
+}
+
+}  // namespace
+
+size_t sprinkle_ws_bytes(int region, int64_t n) { return layout(region, n, nullptr, nullptr); }
+
+cs_status launch_sprinkle(int region, double eta0, uint64_t seed, int64_t n, double* coords,
+                          void* ws, hipStream_t st) {
+  SprinkleWs w;
+  layout(region, n, ws, &w);
+  const int64_t P = pow2_at_least(n);
+  const int planes = coord_planes(region);
+  const unsigned gridP = (unsigned)ceil_div(P, kBlock);
+  if (region == CS_MINK2_DIAMOND) {
+    hipLaunchKernelGGL(k_sprinkle_mink2, dim3(gridP), dim3(kBlock), 0, st,
+                       sm_stream_key(seed, kStreamMink2), n, P, w.raw, w.keys, w.gens);
+    CS_LAUNCH_CHECK();
+  } else if (region == CS_MINK4_DIAMOND) {
+    const int64_t M = mink4_candidates(n);
+    const int64_t nblk = M / kBlock;
+    const uint64_t skey = sm_stream_key(seed, kStreamMink4);
+    hipLaunchKernelGGL(k_mink4_count, dim3((unsigned)nblk), dim3(kBlock), 0, st, skey,
+                       w.blk_count);
+    CS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, w.blk_count, nblk, w.blk_offset);
+    CS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mink4_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, st, skey, n,
+                       w.blk_offset, w.raw, w.keys, w.gens);
+    CS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mink4_tail, dim3(1), dim3(kBlock), 0, st, skey, n, M,
+                       w.blk_offset + nblk, w.raw, w.keys, w.gens);
+    CS_LAUNCH_CHECK();
+    if (P > n) {
+      hipLaunchKernelGGL(k_pad_keys, dim3((unsigned)ceil_div(P - n, kBlock)), dim3(kBlock), 0, st,
+                         n, P, w.keys, w.gens);
+      CS_LAUNCH_CHECK();
+    }
+  } else {
+    hipLaunchKernelGGL(k_sprinkle_ds4, dim3(gridP), dim3(kBlock), 0, st,
+                       sm_stream_key(seed, kStreamDsTime), sm_stream_key(seed, kStreamDsSphere),
+                       tan(eta0), n, P, w.raw, w.keys, w.gens);
+    CS_LAUNCH_CHECK();
+  }
+  cs_status s = bitonic_sort(w.keys, w.gens, P, st);
+  if (s != CS_OK) return s;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, st, w.raw,
+                     w.gens, planes, n, coords);
+  CS_LAUNCH_CHECK();
+  return CS_OK;
+}
+
+}  // namespace cs

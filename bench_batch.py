@@ -1,0 +1,110 @@
+"""Ensemble leg of bench.py: 256 independent 1+1 diamonds, N uniform in [512, 8192].
+
+One HIP-graph launch of the batch pipeline (sprinkle, matrix, counts, actions for
+every instance) against the same 256 instances as separate per-instance calls of
+the single-instance entry points.  Both are timed with HIP events on one stream.
+"""
+from __future__ import annotations
+
+import os
+import tempfile
+
+import numpy as np
+
+import workloads as W
+
+
+def run_batch(cs, torch, dev, stream, reps: int = 5):
+    cfg = W.WORKLOADS["batch_mink2_256"]
+    sizes, seeds = W.batch_instances(cfg["seed"], cfg["count"], cfg["nmin"], cfg["nmax"])
+    eps = (0.0,) + tuple(cfg["eps"])
+    count = len(sizes)
+
+    tune = os.path.join(tempfile.gettempdir(), "cs_tune_gfx950.json")
+    cs.cs_autotune(tune, stream=stream)
+    torch.cuda.synchronize()
+    import json
+    tuned = json.load(open(tune))
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    out = {"instances": count, "n_range": [int(sizes.min()), int(sizes.max())],
+           "tile256_min_n": tuned["tile256_min_n"]}
+    results = {}
+    for name, counter in (("mfma", cs.CS_COUNT_MFMA), ("bitset", cs.CS_COUNT_BITSET)):
+        plan = cs.BatchPlan(sizes, counter=counter, eps=eps, tune_cache=tune)
+        s = torch.from_numpy(seeds.view(np.int64)).to(dev)
+        hist = torch.empty(plan.hist_len, dtype=torch.int64, device=dev)
+        acts = torch.empty(count * len(eps), dtype=torch.float64, device=dev)
+        ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=dev)
+        g = plan.graph(s, hist, acts, ws)
+        for _ in range(2):
+            g.launch(stream)
+        times = []
+        for _ in range(reps):
+            a, b = ev(), ev()
+            a.record(stream)
+            g.launch(stream)
+            b.record(stream)
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        results[name] = (hist.cpu().numpy().view(np.uint64).copy(), plan.offsets)
+        out[f"graph_{name}_ms"] = min(times)
+        out[f"graph_{name}_ensembles_per_s"] = count / (min(times) * 1e-3)
+        out[f"graph_{name}_relations_per_s"] = float(
+            results[name][0].sum()) / (min(times) * 1e-3)
+        del g, plan
+
+    # Per-instance baseline: the single-instance entry points, one instance at a time.
+    nmax = int(sizes.max())
+    ld = cs.cs_ld_words(nmax)
+    L = cs.lib()
+    coords = torch.empty(2 * nmax, dtype=torch.float64, device=dev)
+    bits = torch.empty(nmax * ld, dtype=torch.int64, device=dev)
+    hist1 = torch.empty(nmax, dtype=torch.int64, device=dev)
+    acts1 = torch.empty(len(eps), dtype=torch.float64, device=dev)
+    sp_ws = torch.empty(L.cs_sprinkle_workspace_bytes(0, nmax), dtype=torch.uint8, device=dev)
+    h_ws = torch.empty(L.cs_histogram_workspace_bytes(nmax, 1), dtype=torch.uint8, device=dev)
+    B = cs.binding
+    last = {}
+
+    def one_pass(keep=False):
+        for k in range(count):
+            n = int(sizes[k])
+            ldk = cs.cs_ld_words(n)
+            B._check(L.cs_sprinkle(0, 1.2, int(seeds[k]), n, B._ptr(coords), B._ptr(sp_ws),
+                                   sp_ws.numel(), B._stream(stream)), "sprinkle")
+            B._check(L.cs_causal_matrix(0, B._ptr(coords), n, B._ptr(bits), ldk, B._stream(stream)),
+                     "matrix")
+            B._check(L.cs_interval_histogram(B._ptr(bits), n, ldk, 1, B._ptr(hist1), B._ptr(h_ws),
+                                             h_ws.numel(), B._stream(stream)), "hist")
+            for e, x in enumerate(eps):
+                B._check(L.cs_action(B._ptr(hist1), n, 2, float(x),
+                                     ctypes_ptr(acts1, e), B._stream(stream)), "action")
+            if keep and k < 4:
+                torch.cuda.synchronize()
+                last[k] = hist1[:n - 1].cpu().numpy().view(np.uint64).copy()
+
+    one_pass(keep=True)
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record(stream)
+    one_pass()
+    b.record(stream)
+    b.synchronize()
+    seq_ms = a.elapsed_time(b)
+    out["per_instance_ms"] = seq_ms
+    out["per_instance_ensembles_per_s"] = count / (seq_ms * 1e-3)
+    out["graph_vs_per_instance"] = seq_ms / out["graph_mfma_ms"]
+    hm, offs = results["mfma"]
+    hb, _ = results["bitset"]
+    out["mfma_equals_bitset"] = bool(np.array_equal(hm, hb))
+    out["per_instance_equals_graph"] = all(
+        np.array_equal(last[k], hm[offs[k]:offs[k] + int(sizes[k]) - 1]) for k in last)
+    return out
+
+
+def ctypes_ptr(t, index):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr() + index * t.element_size())

@@ -135,7 +135,8 @@ cs_status cs_action(const uint64_t *hist, int64_t n, int dim, double eps, double
 
 /* ---------------------------------------------------------------------------------
  * Ensembles: `count` independent 1+1 diamonds of sizes n[k] (2 <= n[k] <= 8192).
- * cs_batch_plan builds a host-side plan (sizes, offsets, work list, tile choice).
+ * cs_batch_plan builds a plan (sizes, offsets, work lists, tile choice); its work
+ * tables are uploaded once to device memory that the plan owns (freed by cs_batch_free).
  * cs_batch_run enqueues the whole pipeline -- sprinkle, matrix, counts, actions --
  * as a fixed sequence of kernels with no host synchronisation and no allocation, so
  * the caller may capture it in a HIP graph.
@@ -149,13 +150,38 @@ cs_status cs_action(const uint64_t *hist, int64_t n, int dim, double eps, double
 typedef struct cs_batch_plan_t *cs_batch_plan_handle;
 
 cs_status cs_batch_plan(int64_t count, const int64_t *n /* host */, int counter,
-                        int n_eps, const double *eps /* host */, cs_batch_plan_handle *plan);
+                        int n_eps, const double *eps /* host */, const char *tune_cache,
+                        cs_batch_plan_handle *plan);
 size_t cs_batch_workspace_bytes(cs_batch_plan_handle plan);
 int64_t cs_batch_hist_len(cs_batch_plan_handle plan);
 int64_t cs_batch_hist_offset(cs_batch_plan_handle plan, int64_t k);
 cs_status cs_batch_run(cs_batch_plan_handle plan, const uint64_t *seeds, uint64_t *hist,
                        double *actions, void *workspace, size_t workspace_bytes, void *stream);
 cs_status cs_batch_free(cs_batch_plan_handle plan);
+
+/*
+ * HIP graph of one cs_batch_run with these buffers, captured on an internal stream and
+ * instantiated (so the graph replays the same five launches: fills, sprinkle, build,
+ * count, action).  graph_exec receives an opaque hipGraphExec_t owned by the caller:
+ * launch it with cs_batch_graph_launch on any stream, release it with
+ * cs_batch_graph_destroy.  The buffers must stay valid while the graph is in use.
+ */
+cs_status cs_batch_graph_create(cs_batch_plan_handle plan, const uint64_t *seeds, uint64_t *hist,
+                                double *actions, void *workspace, size_t workspace_bytes,
+                                void **graph_exec);
+cs_status cs_batch_graph_launch(void *graph_exec, void *stream);
+cs_status cs_batch_graph_destroy(void *graph_exec);
+
+/*
+ * Tile autotuner (project-written): on the current device, times the MFMA counter with
+ * 128x128 and 256x256 output tiles on ensembles of 16 diamonds at each size of a fixed
+ * ladder (512 .. 8192 points, best of three launches each, HIP events on `stream`) and
+ * writes JSON {"tile256_min_n": N, "ms": [...]} to cache_path: the smallest size from
+ * which the 256 tiles are faster at every larger size.  It allocates and frees its own
+ * device memory and synchronises `stream`.  cs_batch_plan reads `tune_cache` (may be
+ * NULL: then instances with n >= 4096 use 256 tiles).
+ */
+cs_status cs_autotune(const char *cache_path, void *stream);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,8 @@ SYMBOLS = [
     "cs_coord_planes", "cs_ld_words", "cs_status_string", "cs_sprinkle_workspace_bytes",
     "cs_sprinkle", "cs_causal_matrix", "cs_histogram_workspace_bytes", "cs_interval_histogram",
     "cs_action", "cs_batch_plan", "cs_batch_workspace_bytes", "cs_batch_hist_len",
-    "cs_batch_hist_offset", "cs_batch_run", "cs_batch_free",
+    "cs_batch_hist_offset", "cs_batch_run", "cs_batch_free", "cs_batch_graph_create",
+    "cs_batch_graph_launch", "cs_batch_graph_destroy", "cs_autotune",
 ]
 
 
@@ -54,12 +55,16 @@ def lib():
             "cs_histogram_workspace_bytes": (sz, [i64, c_int]),
             "cs_interval_histogram": (c_int, [p, i64, i64, c_int, p, p, sz, p]),
             "cs_action": (c_int, [p, i64, c_int, dbl, p, p]),
-            "cs_batch_plan": (c_int, [i64, p, c_int, c_int, p, ctypes.POINTER(p)]),
+            "cs_batch_plan": (c_int, [i64, p, c_int, c_int, p, ctypes.c_char_p, ctypes.POINTER(p)]),
             "cs_batch_workspace_bytes": (sz, [p]),
             "cs_batch_hist_len": (i64, [p]),
             "cs_batch_hist_offset": (i64, [p, i64]),
             "cs_batch_run": (c_int, [p, p, p, p, p, sz, p]),
             "cs_batch_free": (c_int, [p]),
+            "cs_batch_graph_create": (c_int, [p, p, p, p, p, sz, ctypes.POINTER(p)]),
+            "cs_batch_graph_launch": (c_int, [p, p]),
+            "cs_batch_graph_destroy": (c_int, [p]),
+            "cs_autotune": (c_int, [ctypes.c_char_p, p]),
         }
         for name, (res, args) in sig.items():
             if hasattr(L, name):
@@ -159,14 +164,15 @@ def cs_action(hist: torch.Tensor, n: int, dim: int, eps: float = 0.0,
 class BatchPlan:
     """Host-side plan of an ensemble of 1+1 diamonds (wraps cs_batch_plan)."""
 
-    def __init__(self, sizes, counter: int = CS_COUNT_MFMA, eps=(0.0,)):
+    def __init__(self, sizes, counter: int = CS_COUNT_MFMA, eps=(0.0,), tune_cache=None):
         import numpy as np
         self.sizes = np.ascontiguousarray(sizes, dtype=np.int64)
         self.eps = np.ascontiguousarray(eps, dtype=np.float64)
         self.count = len(self.sizes)
         h = ctypes.c_void_p()
+        tc = tune_cache.encode() if tune_cache else None
         _check(lib().cs_batch_plan(self.count, self.sizes.ctypes.data_as(ctypes.c_void_p), counter,
-                                   len(self.eps), self.eps.ctypes.data_as(ctypes.c_void_p),
+                                   len(self.eps), self.eps.ctypes.data_as(ctypes.c_void_p), tc,
                                    ctypes.byref(h)), "cs_batch_plan")
         self.handle = h
         self.ws_bytes = lib().cs_batch_workspace_bytes(h)
@@ -179,9 +185,39 @@ class BatchPlan:
                                   _ptr(workspace), workspace.numel(), _stream(stream)),
                "cs_batch_run")
 
+    def graph(self, seeds: torch.Tensor, hist: torch.Tensor, actions: torch.Tensor,
+              workspace: torch.Tensor) -> "BatchGraph":
+        g = ctypes.c_void_p()
+        _check(lib().cs_batch_graph_create(self.handle, _ptr(seeds), _ptr(hist), _ptr(actions),
+                                           _ptr(workspace), workspace.numel(), ctypes.byref(g)),
+               "cs_batch_graph_create")
+        return BatchGraph(g, (seeds, hist, actions, workspace, self))
+
     def __del__(self):
         try:
             if getattr(self, "handle", None) is not None and self.handle.value:
                 lib().cs_batch_free(self.handle)
         except Exception:
             pass
+
+
+class BatchGraph:
+    """An instantiated HIP graph of one ensemble run (wraps cs_batch_graph_*)."""
+
+    def __init__(self, handle, keepalive):
+        self.handle = handle
+        self._keep = keepalive
+
+    def launch(self, stream=None):
+        _check(lib().cs_batch_graph_launch(self.handle, _stream(stream)), "cs_batch_graph_launch")
+
+    def __del__(self):
+        try:
+            if self.handle is not None and self.handle.value:
+                lib().cs_batch_graph_destroy(self.handle)
+        except Exception:
+            pass
+
+
+def cs_autotune(cache_path: str, stream=None):
+    _check(lib().cs_autotune(cache_path.encode(), _stream(stream)), "cs_autotune")

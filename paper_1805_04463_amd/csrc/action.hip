@@ -123,8 +123,9 @@ __device__ inline dd small_weight(const Smear& s, int64_t m) {
 
 constexpr int kActThreads = 1024;
 
-__global__ __launch_bounds__(kActThreads) void k_action(const uint64_t* __restrict__ hist, int64_t n,
-                                                        int dim, double eps, double* __restrict__ out) {
+// The action of one histogram by one workgroup of kActThreads threads.
+__device__ inline void action_block(const uint64_t* __restrict__ hist, int64_t n, int dim, double eps,
+                                    double* __restrict__ out, double* s_hi, double* s_lo) {
   const int64_t nb = n - 1;
   if (eps == 0.0) {
     if (threadIdx.x == 0) {
@@ -151,7 +152,6 @@ __global__ __launch_bounds__(kActThreads) void k_action(const uint64_t* __restri
     }
     return;
   }
-  __shared__ double s_hi[kActThreads], s_lo[kActThreads];
   Smear sm;
   sm.dim = dim;
   sm.e = {eps, 0.0};
@@ -207,11 +207,37 @@ __global__ __launch_bounds__(kActThreads) void k_action(const uint64_t* __restri
   }
 }
 
+__global__ __launch_bounds__(kActThreads) void k_action(const uint64_t* __restrict__ hist, int64_t n,
+                                                        int dim, double eps, double* __restrict__ out) {
+  __shared__ double s_hi[kActThreads], s_lo[kActThreads];
+  action_block(hist, n, dim, eps, out, s_hi, s_lo);
+}
+
+// Ensemble: block k * n_eps + e evaluates eps[e] for instance k.
+__global__ __launch_bounds__(kActThreads) void k_action_batch(const uint64_t* __restrict__ hist,
+                                                              const BatchInst* __restrict__ inst,
+                                                              int dim, const double* __restrict__ eps,
+                                                              int n_eps, double* __restrict__ out) {
+  __shared__ double s_hi[kActThreads], s_lo[kActThreads];
+  const int k = blockIdx.x / n_eps, e = blockIdx.x % n_eps;
+  const BatchInst d = inst[k];
+  action_block(hist + d.hist_off, d.n, dim, eps[e], out + blockIdx.x, s_hi, s_lo);
+}
+
 }  // namespace
 
 cs_status launch_action(const uint64_t* hist, int64_t n, int dim, double eps, double* out,
                         hipStream_t st) {
   hipLaunchKernelGGL(k_action, dim3(1), dim3(kActThreads), 0, st, hist, n, dim, eps, out);
+  CS_LAUNCH_CHECK();
+  return CS_OK;
+}
+
+cs_status launch_action_batch(const uint64_t* hist, const BatchInst* inst, int64_t count, int dim,
+                              const double* eps, int n_eps, double* out, hipStream_t st) {
+  if (count <= 0 || n_eps <= 0) return CS_OK;
+  hipLaunchKernelGGL(k_action_batch, dim3((unsigned)(count * n_eps)), dim3(kActThreads), 0, st, hist,
+                     inst, dim, eps, n_eps, out);
   CS_LAUNCH_CHECK();
   return CS_OK;
 }

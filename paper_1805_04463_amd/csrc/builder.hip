@@ -73,13 +73,14 @@ __device__ inline bool precedes(const Pt<CS_DS4_SLAB>& a, const Pt<CS_DS4_SLAB>&
 
 constexpr int kWavesPerBlock = 4;
 
+// One wave: the 64x64 block (bi, bj), bi <= bj, of an n-point matrix S with stride ld.
+// The wave owning the last column block of a row block also zeroes that row block's
+// padding words [nb, ld), so every word of S is written exactly once.
 template <int R>
-__global__ __launch_bounds__(256) void k_build(const double* __restrict__ coords, int64_t n,
-                                               uint64_t* __restrict__ S, int64_t ld, int64_t nb) {
+__device__ inline void build_block(const double* __restrict__ coords, int64_t n,
+                                   uint64_t* __restrict__ S, int64_t ld, int64_t nb, int64_t bi,
+                                   int64_t bj) {
   const int lane = threadIdx.x & 63;
-  const int64_t bi = blockIdx.y;
-  const int64_t bj = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (bj >= nb || bj < bi) return;  // wave-uniform exit; no barriers below
   const int64_t j = bj * 64 + lane;
   const bool jv = j < n;
   Pt<R> pj = load_pt(coords, n, jv ? j : n - 1, (Pt<R>*)nullptr);
@@ -101,15 +102,31 @@ __global__ __launch_bounds__(256) void k_build(const double* __restrict__ coords
     if (irow < n) S[irow * ld + bj] = rowword;
     if (jv) S[j * ld + bi] = colword;
   }
+  if (bj == nb - 1 && irow < n)
+    for (int64_t w = nb; w < ld; ++w) S[irow * ld + w] = 0;
 }
 
-// Zero the padding words [nb, ld) of every row.
-__global__ void k_zero_pad(uint64_t* __restrict__ S, int64_t n, int64_t ld, int64_t nb) {
-  const int64_t padw = ld - nb;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * padw) return;
-  int64_t row = t / padw, w = nb + t % padw;
-  S[row * ld + w] = 0;
+template <int R>
+__global__ __launch_bounds__(256) void k_build(const double* __restrict__ coords, int64_t n,
+                                               uint64_t* __restrict__ S, int64_t ld, int64_t nb) {
+  const int64_t bi = blockIdx.y;
+  const int64_t bj = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (bj >= nb || bj < bi) return;  // wave-uniform exit; no barriers
+  build_block<R>(coords, n, S, ld, nb, bi, bj);
+}
+
+// Ensemble of 1+1 diamonds: wave w of block b takes work item 4b + w, packed as
+// instance << 16 | bi << 8 | bj.
+__global__ __launch_bounds__(256) void k_build_batch(const double* __restrict__ coords,
+                                                     const BatchInst* __restrict__ inst,
+                                                     const uint32_t* __restrict__ items,
+                                                     int64_t nitems, uint64_t* __restrict__ bits) {
+  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (t >= nitems) return;
+  const uint32_t it = items[t];
+  const BatchInst d = inst[it >> 16];
+  build_block<CS_MINK2_DIAMOND>(coords + d.coord_off, d.n, bits + d.bits_off, d.ld,
+                                ceil_div(d.n, 64), (it >> 8) & 255u, it & 255u);
 }
 
 template <int R>
@@ -118,12 +135,6 @@ cs_status launch_build(const double* coords, int64_t n, uint64_t* S, int64_t ld,
   dim3 grid((unsigned)ceil_div(nb, kWavesPerBlock), (unsigned)nb);
   hipLaunchKernelGGL(k_build<R>, grid, dim3(64 * kWavesPerBlock), 0, st, coords, n, S, ld, nb);
   CS_LAUNCH_CHECK();
-  if (ld > nb) {
-    int64_t tot = n * (ld - nb);
-    hipLaunchKernelGGL(k_zero_pad, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, st, S, n, ld,
-                       nb);
-    CS_LAUNCH_CHECK();
-  }
   return CS_OK;
 }
 
@@ -137,6 +148,15 @@ cs_status launch_causal_matrix(int region, const double* coords, int64_t n, uint
     case CS_DS4_SLAB: return launch_build<CS_DS4_SLAB>(coords, n, bits, ld, st);
     default: return CS_ERR_UNSUPPORTED;
   }
+}
+
+cs_status launch_build_batch(const double* coords, const BatchInst* inst, const uint32_t* items,
+                             int64_t nitems, uint64_t* bits, hipStream_t st) {
+  if (nitems <= 0) return CS_OK;
+  hipLaunchKernelGGL(k_build_batch, dim3((unsigned)ceil_div(nitems, kWavesPerBlock)),
+                     dim3(64 * kWavesPerBlock), 0, st, coords, inst, items, nitems, bits);
+  CS_LAUNCH_CHECK();
+  return CS_OK;
 }
 
 }  // namespace cs

@@ -74,6 +74,17 @@ inline int coord_planes(int region) {
     if (_e != hipSuccess) return CS_ERR_HIP;                \
   } while (0)
 
+// One instance of an ensemble: size, row stride (uint64 words) and offsets of its
+// coordinates (doubles), matrix (uint64 words) and histogram (uint64 bins) in the
+// concatenated buffers.
+struct BatchInst {
+  int64_t n, ld, coord_off, bits_off, hist_off;
+};
+
+// Largest instance of an ensemble (its whole histogram fits the LDS bins, its sort
+// fits one workgroup's LDS).
+constexpr int64_t kBatchMaxN = 8192;
+
 // ---------------------------------------------------------------------------
 // Internal launchers (each returns CS_OK or CS_ERR_HIP).
 // ---------------------------------------------------------------------------
@@ -89,5 +100,19 @@ cs_status launch_action(const uint64_t* hist, int64_t n, int dim, double eps, do
                         hipStream_t st);
 cs_status launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream_t st);
 int device_cu_count();
+
+// Ensemble pieces (1+1 diamonds).
+cs_status launch_sprinkle_batch(const uint64_t* seeds, const BatchInst* inst, int64_t count,
+                                double* coords, hipStream_t st);
+cs_status launch_build_batch(const double* coords, const BatchInst* inst,
+                             const uint32_t* items, int64_t nitems, uint64_t* bits,
+                             hipStream_t st);
+// mode 0: bitset counter (128 tiles); 2 / 4: MFMA counter with 128 / 256 tiles.
+cs_status launch_count_batch(int mode, const uint64_t* bits, const BatchInst* inst,
+                             const uint32_t* items, int64_t nitems, uint64_t* hist,
+                             unsigned int* counter, hipStream_t st);
+cs_status launch_action_batch(const uint64_t* hist, const BatchInst* inst, int64_t count,
+                              int dim, const double* eps, int n_eps, double* out,
+                              hipStream_t st);
 
 }  // namespace cs

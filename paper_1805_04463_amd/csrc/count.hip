@@ -67,24 +67,38 @@ __device__ inline uint32_t mask_below(int64_t kw, int64_t g) {
 // words; the half index is XOR-swizzled with bit 3 of the row to spread banks.
 __device__ inline int lds_pos(int r, int h) { return r * kStageWords + ((h ^ ((r >> 3) & 1)) << 2); }
 
-// Global -> register fetch of one stage for a panel of ROWS rows starting at row0.
-// Each thread fetches ROWS*2/kThreads halves (16 bytes each).
+// Global -> register fetch of K stages for a panel of ROWS rows starting at row0.
+// Each thread owns ROWS*2/kThreads 16-byte halves (row r = c/2, half h = c%2); its
+// row pointers are set once per tile.  The triangular masks only matter on stages
+// that overlap the panel's own diagonal block, so they are applied only there.
 template <int ROWS>
 struct Stage {
   static constexpr int kPer = ROWS * 2 / kThreads;
   uint4 v[kPer];
+  const uint4* p[kPer];
 
-  __device__ inline void fetch(const uint32_t* __restrict__ S32, int64_t ld32, int64_t row0,
-                               int64_t n, int64_t kbit0, bool above) {
+  __device__ inline void init(const uint32_t* __restrict__ S32, int64_t ld32, int64_t row0,
+                              int64_t n, int64_t kbit0) {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int c = threadIdx.x + q * kThreads;
-      const int r = c >> 1, h = c & 1;
-      const int64_t g = row0 + r;
+      const int64_t g = row0 + (c >> 1);
+      p[q] = g < n ? (const uint4*)(S32 + g * ld32 + (kbit0 >> 5)) + (c & 1) : nullptr;
+    }
+  }
+  // Stage s covers bits [kb, kb + 256), kb = kbit0 + 256 s.  above: keep k > row (A side),
+  // else keep k < row (B side).
+  __device__ inline void fetch(int64_t s, int64_t kb, int64_t row_bits, int64_t row0,
+                               bool masked, bool above) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int c = threadIdx.x + q * kThreads;
+      const int h = c & 1;
+      const int64_t kw = kb + h * 128;
       uint4 x = make_uint4(0, 0, 0, 0);
-      const int64_t kw = kbit0 + h * 128;
-      if (g < n && kw < ld32 * 32) {
-        x = *(const uint4*)(S32 + g * ld32 + (kw >> 5));
+      if (p[q] != nullptr && kw < row_bits) x = p[q][2 * s];
+      if (masked) {
+        const int64_t g = row0 + (c >> 1);
         if (above) {
           x.x &= mask_above(kw, g);
           x.y &= mask_above(kw + 32, g);
@@ -110,18 +124,28 @@ struct Stage {
 };
 
 // Counts are at most n-2 by construction; the bound check keeps a histogram write in
-// range whatever the inputs.
+// range whatever the inputs.  `tmax` tracks the largest LDS bin this thread touched.
 __device__ inline void bin_add(uint32_t* lds_hist, unsigned long long* hist, uint32_t bin,
-                               int64_t nbins) {
-  if (bin < (uint32_t)kLdsBins)
+                               int64_t nbins, uint32_t& tmax) {
+  if (bin < (uint32_t)kLdsBins) {
     atomicAdd(lds_hist + bin, 1u);
-  else if ((int64_t)bin < nbins)
+    tmax = bin > tmax ? bin : tmax;
+  } else if ((int64_t)bin < nbins) {
     atomicAdd(hist + bin, 1ull);
+  }
 }
 
-__device__ inline void flush_hist(uint32_t* lds_hist, unsigned long long* hist, int64_t nbins) {
+// Adds the LDS bins [0, max touched] to the global histogram and clears them.
+__device__ inline void flush_hist(uint32_t* lds_hist, unsigned long long* hist, int64_t nbins,
+                                  uint32_t& tmax, uint32_t* s_max) {
   __syncthreads();
-  const int lim = (int)(nbins < kLdsBins ? nbins : kLdsBins);
+  if (threadIdx.x == 0) *s_max = 0;
+  __syncthreads();
+  atomicMax(s_max, tmax);
+  __syncthreads();
+  int64_t lim = (int64_t)*s_max + 1;
+  lim = lim < nbins ? lim : nbins;
+  lim = lim < kLdsBins ? lim : kLdsBins;
   for (int b = threadIdx.x; b < lim; b += kThreads) {
     uint32_t v = lds_hist[b];
     if (v) {
@@ -129,10 +153,11 @@ __device__ inline void flush_hist(uint32_t* lds_hist, unsigned long long* hist, 
       lds_hist[b] = 0;
     }
   }
+  tmax = 0;
   __syncthreads();
 }
 
-// Takes the next tile index for the workgroup (one atomic per tile).
+// Takes the next work index for the workgroup (one atomic per tile).
 __device__ inline int64_t next_tile(unsigned int* counter, int* slot) {
   __syncthreads();
   if (threadIdx.x == 0) *slot = (int)atomicAdd(counter, 1u);
@@ -140,251 +165,325 @@ __device__ inline int64_t next_tile(unsigned int* counter, int* slot) {
   return *slot;
 }
 
+struct TileArgs {
+  const uint32_t* S32;        // instance matrix, as 32-bit words
+  int64_t ld32;               // row stride in 32-bit words
+  int64_t n;                  // points of the instance
+  int64_t I0, J0;             // first row / first column of the output tile
+  unsigned long long* hist;   // instance histogram (n-1 bins)
+};
+
 // ===========================================================================
-// MFMA counter.  Workgroup tile BM x BM, four waves in 2x2, each WM x WM blocks of
+// MFMA tile.  Workgroup tile BM x BM, four waves in 2x2, each WM x WM blocks of
 // 32x32 outputs (WM = 4: 256x256 tile, 128x128 per wave, 256 int32 accumulators).
+// Returns false (having done nothing) when no pair of the tile is related.
 // ===========================================================================
+template <int WM>
+__device__ inline bool mfma_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs,
+                                 uint32_t* lds_hist, uint32_t& tmax) {
+  constexpr int BM = 2 * WM * 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int hsel = lane >> 5, l32 = lane & 31;
+  const int64_t n = ta.n, I0 = ta.I0, J0 = ta.J0, nbins = n - 1;
+  const int64_t rb = I0 + wr * (WM * 32);  // first output row of this wave
+
+  // Related bits S[j][i] for this wave's outputs: word mb of column block nb.
+  uint32_t relw[WM][WM];
+  bool any = false;
+#pragma unroll
+  for (int nb = 0; nb < WM; ++nb) {
+    const int64_t j = J0 + wc * (WM * 32) + nb * 32 + l32;
+#pragma unroll
+    for (int mb = 0; mb < WM; ++mb) {
+      uint32_t w = 0;
+      if (j < n) {
+        const int64_t i0 = rb + mb * 32;
+        w = ta.S32[j * ta.ld32 + (i0 >> 5)];
+        w &= mask_below(i0, j);  // only i < j
+      }
+      relw[nb][mb] = w;
+      any |= (w != 0);
+    }
+  }
+  if (!__syncthreads_or(any)) return false;
+
+  v16i acc[WM][WM];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WM; ++b) acc[a][b] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+
+  const int64_t kbeg = I0;
+  const int64_t kend = (J0 + BM < n ? J0 + BM : n);
+  const int64_t nst = ceil_div(kend - kbeg, kStageBits);
+  const int64_t row_bits = ta.ld32 * 32;
+  Stage<BM> sa, sb;
+  sa.init(ta.S32, ta.ld32, I0, n, kbeg);
+  sb.init(ta.S32, ta.ld32, J0, n, kbeg);
+  sa.fetch(0, kbeg, row_bits, I0, kbeg < I0 + BM, true);
+  sb.fetch(0, kbeg, row_bits, J0, kbeg + kStageBits > J0, false);
+  for (int64_t s = 0; s < nst; ++s) {
+    __syncthreads();
+    sa.store(As);
+    sb.store(Bs);
+    __syncthreads();
+    if (s + 1 < nst) {
+      const int64_t kb = kbeg + (s + 1) * kStageBits;
+      sa.fetch(s + 1, kb, row_bits, I0, kb < I0 + BM, true);
+      sb.fetch(s + 1, kb, row_bits, J0, kb + kStageBits > J0, false);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint4 aw[WM], bw[WM];
+#pragma unroll
+      for (int mb = 0; mb < WM; ++mb)
+        aw[mb] = *(const uint4*)(As + lds_pos(wr * WM * 32 + mb * 32 + l32, h));
+#pragma unroll
+      for (int nb = 0; nb < WM; ++nb)
+        bw[nb] = *(const uint4*)(Bs + lds_pos(wc * WM * 32 + nb * 32 + l32, h));
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        v4i af[WM], bf[WM];
+        const uint32_t sh = 4u * (uint32_t)hsel;
+#pragma unroll
+        for (int mb = 0; mb < WM; ++mb) {
+          const uint32_t x = w == 0 ? aw[mb].x : w == 1 ? aw[mb].y : w == 2 ? aw[mb].z : aw[mb].w;
+          af[mb] = (v4i){(int)((x >> sh) & 0x01010101u), (int)((x >> (sh + 1)) & 0x01010101u),
+                         (int)((x >> (sh + 2)) & 0x01010101u), (int)((x >> (sh + 3)) & 0x01010101u)};
+        }
+#pragma unroll
+        for (int nb = 0; nb < WM; ++nb) {
+          const uint32_t x = w == 0 ? bw[nb].x : w == 1 ? bw[nb].y : w == 2 ? bw[nb].z : bw[nb].w;
+          bf[nb] = (v4i){(int)((x >> sh) & 0x01010101u), (int)((x >> (sh + 1)) & 0x01010101u),
+                         (int)((x >> (sh + 2)) & 0x01010101u), (int)((x >> (sh + 3)) & 0x01010101u)};
+        }
+#pragma unroll
+        for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < WM; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[mb], bf[nb], acc[mb][nb], 0, 0, 0);
+      }
+    }
+  }
+
+  // Epilogue.  32x32 accumulator layout: lane holds column (lane & 31) and rows
+  // 8*(e/4) + 4*(lane/32) + (e%4) for e = 0..15.
+#pragma unroll
+  for (int nb = 0; nb < WM; ++nb) {
+#pragma unroll
+    for (int mb = 0; mb < WM; ++mb) {
+      const uint32_t w = relw[nb][mb];
+      if (!w) continue;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int il = (e >> 2) * 8 + hsel * 4 + (e & 3);
+        if ((w >> il) & 1u) bin_add(lds_hist, ta.hist, (uint32_t)acc[mb][nb][e], nbins, tmax);
+      }
+    }
+  }
+  return true;
+}
+
+// ===========================================================================
+// Bitset tile.  Workgroup tile 128 x 128; thread (ty, tx) = (tid/16, tid%16) owns
+// rows 8*ty + a and columns tx + 16*b (a, b = 0..7); a wave whose 32 x 128 pairs
+// hold no relation skips the arithmetic (it still helps stage).
+// ===========================================================================
+constexpr int kBitsetTile = 128;
+
+__device__ inline bool bitset_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs,
+                                   uint32_t* lds_hist, uint32_t& tmax) {
+  constexpr int BM = kBitsetTile;
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const int64_t n = ta.n, I0 = ta.I0, J0 = ta.J0, nbins = n - 1;
+
+  // Related bits: for row i = I0 + 8ty + a, the columns tx + 16b are taken from the
+  // row's 128-bit slice over [J0, J0 + 128).
+  uint32_t rel[8];  // bit b of rel[a]: pair (8ty + a, tx + 16b) related
+  bool any = false;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int64_t i = I0 + ty * 8 + a;
+    uint32_t r = 0;
+    if (i < n) {
+      const uint4 x = *(const uint4*)(ta.S32 + i * ta.ld32 + (J0 >> 5));
+      const uint32_t xw[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int c = tx + 16 * b;
+        const int64_t j = J0 + c;
+        if (((xw[c >> 5] >> (c & 31)) & 1u) && i < j) r |= 1u << b;
+      }
+    }
+    rel[a] = r;
+    any |= (r != 0);
+  }
+  const bool wave_any = __any(any);
+  if (!__syncthreads_or(any)) return false;
+
+  uint32_t acc[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[a][b] = 0;
+
+  const int64_t kbeg = I0;
+  const int64_t kend = (J0 + BM < n ? J0 + BM : n);
+  const int64_t nst = ceil_div(kend - kbeg, kStageBits);
+  const int64_t row_bits = ta.ld32 * 32;
+  Stage<BM> sa, sb;
+  sa.init(ta.S32, ta.ld32, I0, n, kbeg);
+  sb.init(ta.S32, ta.ld32, J0, n, kbeg);
+  sa.fetch(0, kbeg, row_bits, I0, kbeg < I0 + BM, true);
+  sb.fetch(0, kbeg, row_bits, J0, kbeg + kStageBits > J0, false);
+  for (int64_t s = 0; s < nst; ++s) {
+    __syncthreads();
+    sa.store(As);
+    sb.store(Bs);
+    __syncthreads();
+    if (s + 1 < nst) {
+      const int64_t kb = kbeg + (s + 1) * kStageBits;
+      sa.fetch(s + 1, kb, row_bits, I0, kb < I0 + BM, true);
+      sb.fetch(s + 1, kb, row_bits, J0, kb + kStageBits > J0, false);
+    }
+    if (!wave_any) continue;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint4 aw[8], bw[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) aw[a] = *(const uint4*)(As + lds_pos(ty * 8 + a, h));
+#pragma unroll
+      for (int b = 0; b < 8; ++b) bw[b] = *(const uint4*)(Bs + lds_pos(tx + 16 * b, h));
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          acc[a][b] += __popc(aw[a].x & bw[b].x);
+          acc[a][b] += __popc(aw[a].y & bw[b].y);
+          acc[a][b] += __popc(aw[a].z & bw[b].z);
+          acc[a][b] += __popc(aw[a].w & bw[b].w);
+        }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+      if ((rel[a] >> b) & 1u) bin_add(lds_hist, ta.hist, acc[a][b], nbins, tmax);
+  return true;
+}
+
+// ===========================================================================
+// Single-instance kernels: persistent over the T(T+1)/2 tiles, longest first.
+// ===========================================================================
+template <int BM>
+struct TileLds {
+  uint32_t As[BM * kStageWords] __attribute__((aligned(16)));
+  uint32_t Bs[BM * kStageWords] __attribute__((aligned(16)));
+  uint32_t hist[kLdsBins];
+  uint32_t maxbin;
+  int slot;
+};
+
 template <int WM>
 __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __restrict__ S,
                                                             int64_t n, int64_t ld,
                                                             unsigned long long* __restrict__ hist,
                                                             unsigned int* __restrict__ counter) {
   constexpr int BM = 2 * WM * 32;
-  __shared__ __attribute__((aligned(16))) uint32_t As[BM * kStageWords];
-  __shared__ __attribute__((aligned(16))) uint32_t Bs[BM * kStageWords];
-  __shared__ uint32_t lds_hist[kLdsBins];
-  __shared__ int slot;
-
-  const uint32_t* S32 = (const uint32_t*)S;
-  const int64_t ld32 = 2 * ld;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int hsel = lane >> 5, l32 = lane & 31;
-  const int64_t nbins = n - 1;
+  __shared__ TileLds<BM> L;
   const int64_t T = ceil_div(n, BM);
   const int64_t ntiles = T * (T + 1) / 2;
-
-  for (int b = threadIdx.x; b < kLdsBins; b += kThreads) lds_hist[b] = 0;
+  for (int b = threadIdx.x; b < kLdsBins; b += kThreads) L.hist[b] = 0;
+  uint32_t tmax = 0;
   int64_t pairs_in_lds = 0;
-
+  TileArgs ta{(const uint32_t*)S, 2 * ld, n, 0, 0, hist};
   for (;;) {
-    const int64_t t = next_tile(counter, &slot);
+    const int64_t t = next_tile(counter, &L.slot);
     if (t >= ntiles) break;
     int64_t I, J;
     tile_of(t, T, &I, &J);
-    const int64_t I0 = I * BM, J0 = J * BM;
-    const int64_t rb = I0 + wr * (WM * 32);  // first output row of this wave
-
-    // Related bits S[j][i] for this wave's outputs: word mb of column block nb.
-    uint32_t relw[WM][WM];
-    bool any = false;
-#pragma unroll
-    for (int nb = 0; nb < WM; ++nb) {
-      const int64_t j = J0 + wc * (WM * 32) + nb * 32 + l32;
-#pragma unroll
-      for (int mb = 0; mb < WM; ++mb) {
-        uint32_t w = 0;
-        if (j < n) {
-          const int64_t i0 = rb + mb * 32;
-          w = S32[j * ld32 + (i0 >> 5)];
-          w &= mask_below(i0, j);  // only i < j
-        }
-        relw[nb][mb] = w;
-        any |= (w != 0);
-      }
-    }
-    if (!__syncthreads_or(any)) continue;
-
-    if (pairs_in_lds > (1ll << 31) - (int64_t)BM * BM) {
-      flush_hist(lds_hist, hist, nbins);
+    if (pairs_in_lds > (1ll << 31) - (int64_t)BM * BM) {  // keep uint32 LDS bins exact
+      flush_hist(L.hist, hist, n - 1, tmax, &L.maxbin);
       pairs_in_lds = 0;
     }
-    pairs_in_lds += (int64_t)BM * BM;
-
-    v16i acc[WM][WM];
-#pragma unroll
-    for (int a = 0; a < WM; ++a)
-#pragma unroll
-      for (int b = 0; b < WM; ++b) acc[a][b] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-
-    const int64_t kbeg = I0;
-    const int64_t kend = (J0 + BM < n ? J0 + BM : n);
-    const int64_t nst = ceil_div(kend - kbeg, kStageBits);
-    Stage<BM> sa, sb;
-    sa.fetch(S32, ld32, I0, n, kbeg, true);
-    sb.fetch(S32, ld32, J0, n, kbeg, false);
-    for (int64_t s = 0; s < nst; ++s) {
-      __syncthreads();
-      sa.store(As);
-      sb.store(Bs);
-      __syncthreads();
-      if (s + 1 < nst) {
-        const int64_t kb = kbeg + (s + 1) * kStageBits;
-        sa.fetch(S32, ld32, I0, n, kb, true);
-        sb.fetch(S32, ld32, J0, n, kb, false);
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        uint4 aw[WM], bw[WM];
-#pragma unroll
-        for (int mb = 0; mb < WM; ++mb)
-          aw[mb] = *(const uint4*)(As + lds_pos(wr * WM * 32 + mb * 32 + l32, h));
-#pragma unroll
-        for (int nb = 0; nb < WM; ++nb)
-          bw[nb] = *(const uint4*)(Bs + lds_pos(wc * WM * 32 + nb * 32 + l32, h));
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          v4i af[WM], bf[WM];
-          const uint32_t sh = 4u * (uint32_t)hsel;
-#pragma unroll
-          for (int mb = 0; mb < WM; ++mb) {
-            const uint32_t x = w == 0 ? aw[mb].x : w == 1 ? aw[mb].y : w == 2 ? aw[mb].z : aw[mb].w;
-            af[mb] = (v4i){(int)((x >> sh) & 0x01010101u), (int)((x >> (sh + 1)) & 0x01010101u),
-                           (int)((x >> (sh + 2)) & 0x01010101u), (int)((x >> (sh + 3)) & 0x01010101u)};
-          }
-#pragma unroll
-          for (int nb = 0; nb < WM; ++nb) {
-            const uint32_t x = w == 0 ? bw[nb].x : w == 1 ? bw[nb].y : w == 2 ? bw[nb].z : bw[nb].w;
-            bf[nb] = (v4i){(int)((x >> sh) & 0x01010101u), (int)((x >> (sh + 1)) & 0x01010101u),
-                           (int)((x >> (sh + 2)) & 0x01010101u), (int)((x >> (sh + 3)) & 0x01010101u)};
-          }
-#pragma unroll
-          for (int mb = 0; mb < WM; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < WM; ++nb)
-              acc[mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[mb], bf[nb], acc[mb][nb], 0, 0, 0);
-        }
-      }
-    }
-
-    // Epilogue.  32x32 accumulator layout: lane holds column (lane & 31) and rows
-    // 8*(e/4) + 4*(lane/32) + (e%4) for e = 0..15.
-#pragma unroll
-    for (int nb = 0; nb < WM; ++nb) {
-#pragma unroll
-      for (int mb = 0; mb < WM; ++mb) {
-        const uint32_t w = relw[nb][mb];
-        if (!w) continue;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int il = (e >> 2) * 8 + hsel * 4 + (e & 3);
-          if ((w >> il) & 1u) bin_add(lds_hist, hist, (uint32_t)acc[mb][nb][e], nbins);
-        }
-      }
-    }
+    ta.I0 = I * BM;
+    ta.J0 = J * BM;
+    if (mfma_tile<WM>(ta, L.As, L.Bs, L.hist, tmax)) pairs_in_lds += (int64_t)BM * BM;
   }
-  flush_hist(lds_hist, hist, nbins);
+  flush_hist(L.hist, hist, n - 1, tmax, &L.maxbin);
 }
 
-// ===========================================================================
-// Bitset counter.  Workgroup tile 128 x 128; thread (ty, tx) = (tid/16, tid%16)
-// owns rows 8*ty + a and columns tx + 16*b (a, b = 0..7).
-// ===========================================================================
 __global__ __launch_bounds__(kThreads, 2) void k_count_bitset(const uint64_t* __restrict__ S,
                                                               int64_t n, int64_t ld,
                                                               unsigned long long* __restrict__ hist,
                                                               unsigned int* __restrict__ counter) {
-  constexpr int BM = 128;
-  __shared__ __attribute__((aligned(16))) uint32_t As[BM * kStageWords];
-  __shared__ __attribute__((aligned(16))) uint32_t Bs[BM * kStageWords];
-  __shared__ uint32_t lds_hist[kLdsBins];
-  __shared__ int slot;
-
-  const uint32_t* S32 = (const uint32_t*)S;
-  const int64_t ld32 = 2 * ld;
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  const int64_t nbins = n - 1;
+  constexpr int BM = kBitsetTile;
+  __shared__ TileLds<BM> L;
   const int64_t T = ceil_div(n, BM);
   const int64_t ntiles = T * (T + 1) / 2;
-
-  for (int b = threadIdx.x; b < kLdsBins; b += kThreads) lds_hist[b] = 0;
+  for (int b = threadIdx.x; b < kLdsBins; b += kThreads) L.hist[b] = 0;
+  uint32_t tmax = 0;
   int64_t pairs_in_lds = 0;
-
+  TileArgs ta{(const uint32_t*)S, 2 * ld, n, 0, 0, hist};
   for (;;) {
-    const int64_t t = next_tile(counter, &slot);
+    const int64_t t = next_tile(counter, &L.slot);
     if (t >= ntiles) break;
     int64_t I, J;
     tile_of(t, T, &I, &J);
-    const int64_t I0 = I * BM, J0 = J * BM;
-
-    // Related bits: for row i = I0 + 8ty + a, the byte of columns tx + 16b is
-    // gathered from the row's 128-bit slice over [J0, J0 + 128).
-    uint32_t rel[8];  // bit b of rel[a]: pair (8ty + a, tx + 16b) related
-    bool any = false;
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int64_t i = I0 + ty * 8 + a;
-      uint32_t r = 0;
-      if (i < n) {
-        const uint4 x = *(const uint4*)(S32 + i * ld32 + (J0 >> 5));
-        const uint32_t xw[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const int c = tx + 16 * b;
-          const int64_t j = J0 + c;
-          if (((xw[c >> 5] >> (c & 31)) & 1u) && i < j) r |= 1u << b;
-        }
-      }
-      rel[a] = r;
-      any |= (r != 0);
-    }
-    const bool wave_any = __any(any);
-    if (!__syncthreads_or(any)) continue;
-
     if (pairs_in_lds > (1ll << 31) - (int64_t)BM * BM) {
-      flush_hist(lds_hist, hist, nbins);
+      flush_hist(L.hist, hist, n - 1, tmax, &L.maxbin);
       pairs_in_lds = 0;
     }
-    pairs_in_lds += (int64_t)BM * BM;
-
-    uint32_t acc[8][8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-      for (int b = 0; b < 8; ++b) acc[a][b] = 0;
-
-    const int64_t kbeg = I0;
-    const int64_t kend = (J0 + BM < n ? J0 + BM : n);
-    const int64_t nst = ceil_div(kend - kbeg, kStageBits);
-    Stage<BM> sa, sb;
-    sa.fetch(S32, ld32, I0, n, kbeg, true);
-    sb.fetch(S32, ld32, J0, n, kbeg, false);
-    for (int64_t s = 0; s < nst; ++s) {
-      __syncthreads();
-      sa.store(As);
-      sb.store(Bs);
-      __syncthreads();
-      if (s + 1 < nst) {
-        const int64_t kb = kbeg + (s + 1) * kStageBits;
-        sa.fetch(S32, ld32, I0, n, kb, true);
-        sb.fetch(S32, ld32, J0, n, kb, false);
-      }
-      if (!wave_any) continue;  // nothing related in this wave's 32 x 128 pairs
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        uint4 aw[8], bw[8];
-#pragma unroll
-        for (int a = 0; a < 8; ++a) aw[a] = *(const uint4*)(As + lds_pos(ty * 8 + a, h));
-#pragma unroll
-        for (int b = 0; b < 8; ++b) bw[b] = *(const uint4*)(Bs + lds_pos(tx + 16 * b, h));
-#pragma unroll
-        for (int a = 0; a < 8; ++a)
-#pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            acc[a][b] += __popc(aw[a].x & bw[b].x);
-            acc[a][b] += __popc(aw[a].y & bw[b].y);
-            acc[a][b] += __popc(aw[a].z & bw[b].z);
-            acc[a][b] += __popc(aw[a].w & bw[b].w);
-          }
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-      for (int b = 0; b < 8; ++b)
-        if ((rel[a] >> b) & 1u) bin_add(lds_hist, hist, acc[a][b], nbins);
+    ta.I0 = I * BM;
+    ta.J0 = J * BM;
+    if (bitset_tile(ta, L.As, L.Bs, L.hist, tmax)) pairs_in_lds += (int64_t)BM * BM;
   }
-  flush_hist(lds_hist, hist, nbins);
+  flush_hist(L.hist, hist, n - 1, tmax, &L.maxbin);
+}
+
+// ===========================================================================
+// Ensemble kernels: persistent over packed work items (instance << 16 | I << 8 | J),
+// ordered longest first across all instances.  The LDS histogram belongs to one
+// instance at a time and is flushed when the workgroup moves to another instance.
+// Instance sizes are at most 8192, so every bin fits in LDS.
+// ===========================================================================
+template <int MODE>  // 0: bitset (128 tiles), 2 / 4: MFMA with WM = MODE
+__global__ __launch_bounds__(kThreads, 1) void k_count_batch(const uint64_t* __restrict__ bits,
+                                                             const BatchInst* __restrict__ inst,
+                                                             const uint32_t* __restrict__ items,
+                                                             int64_t nitems,
+                                                             unsigned long long* __restrict__ hist,
+                                                             unsigned int* __restrict__ counter) {
+  constexpr int BM = MODE == 0 ? kBitsetTile : 2 * MODE * 32;
+  __shared__ TileLds<BM> L;
+  for (int b = threadIdx.x; b < kLdsBins; b += kThreads) L.hist[b] = 0;
+  uint32_t tmax = 0;
+  int cur = -1;
+  TileArgs ta{nullptr, 0, 0, 0, 0, nullptr};
+  for (;;) {
+    const int64_t t = next_tile(counter, &L.slot);
+    if (t >= nitems) break;
+    const uint32_t it = items[t];
+    const int k = (int)(it >> 16);
+    if (k != cur) {
+      if (cur >= 0) flush_hist(L.hist, ta.hist, ta.n - 1, tmax, &L.maxbin);
+      cur = k;
+      const BatchInst d = inst[k];
+      ta.S32 = (const uint32_t*)(bits + d.bits_off);
+      ta.ld32 = 2 * d.ld;
+      ta.n = d.n;
+      ta.hist = hist + d.hist_off;
+    }
+    ta.I0 = (int64_t)((it >> 8) & 255u) * BM;
+    ta.J0 = (int64_t)(it & 255u) * BM;
+    if (MODE == 0)
+      bitset_tile(ta, L.As, L.Bs, L.hist, tmax);
+    else
+      mfma_tile<(MODE == 0 ? 2 : MODE)>(ta, L.As, L.Bs, L.hist, tmax);
+  }
+  if (cur >= 0) flush_hist(L.hist, ta.hist, ta.n - 1, tmax, &L.maxbin);
 }
 
 __global__ void k_fill_u64(uint64_t* __restrict__ p, int64_t count, uint64_t value) {
@@ -441,6 +540,33 @@ cs_status launch_histogram(const uint64_t* bits, int64_t n, int64_t ld, int coun
     unsigned grid = (unsigned)std::min<int64_t>(T * (T + 1) / 2, 2 * cus);
     hipLaunchKernelGGL(k_count_bitset, dim3(grid), dim3(kThreads), 0, st, bits, n, ld,
                        (unsigned long long*)hist, ctr);
+  }
+  CS_LAUNCH_CHECK();
+  return CS_OK;
+}
+
+cs_status launch_count_batch(int mode, const uint64_t* bits, const BatchInst* inst,
+                             const uint32_t* items, int64_t nitems, uint64_t* hist,
+                             unsigned int* counter, hipStream_t st) {
+  if (nitems <= 0) return CS_OK;
+  const int cus = device_cu_count();
+  const int per_cu = mode == 4 ? 1 : 2;  // LDS: 80 KiB (256 tiles) or 72 KiB (128 tiles)
+  unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)cus * per_cu);
+  unsigned long long* h = (unsigned long long*)hist;
+  switch (mode) {
+    case 0:
+      hipLaunchKernelGGL(k_count_batch<0>, dim3(grid), dim3(kThreads), 0, st, bits, inst, items,
+                         nitems, h, counter);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_count_batch<2>, dim3(grid), dim3(kThreads), 0, st, bits, inst, items,
+                         nitems, h, counter);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_count_batch<4>, dim3(grid), dim3(kThreads), 0, st, bits, inst, items,
+                         nitems, h, counter);
+      break;
+    default: return CS_ERR_UNSUPPORTED;
   }
   CS_LAUNCH_CHECK();
   return CS_OK;

@@ -341,6 +341,51 @@ cs_status bitonic_sort(uint64_t* keys, uint32_t* gens, int64_t P, hipStream_t st
   return CS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Ensemble of 1+1 diamonds: one workgroup per instance (n <= 8192).  Keys are
+// sorted in LDS; the sorted coordinates are then regenerated from the sorted
+// generation indices (the generator is counter-based), so no raw copy is kept.
+// ---------------------------------------------------------------------------
+constexpr int kBatchSortThreads = 1024;
+
+__global__ __launch_bounds__(kBatchSortThreads) void k_sprinkle_mink2_batch(
+    const uint64_t* __restrict__ seeds, const BatchInst* __restrict__ inst,
+    double* __restrict__ coords) {
+  __shared__ uint64_t sk[kBatchMaxN];
+  __shared__ uint32_t sg[kBatchMaxN];
+  const BatchInst d = inst[blockIdx.x];
+  const int n = (int)d.n;
+  int P = 2;
+  while (P < n) P <<= 1;
+  const uint64_t skey = sm_stream_key(seeds[blockIdx.x], kStreamMink2);
+  for (int g = threadIdx.x; g < P; g += kBatchSortThreads) {
+    if (g < n) {
+      sk[g] = (sm_output(skey, 2 * (uint64_t)g) >> 11) + (sm_output(skey, 2 * (uint64_t)g + 1) >> 11);
+      sg[g] = (uint32_t)g;
+    } else {
+      sk[g] = ~0ull;
+      sg[g] = 0xFFFFFFFFu;
+    }
+  }
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < P / 2; t += kBatchSortThreads) {
+        const int i = 2 * t - (t & (j - 1));
+        cmp_swap_lds(sk, sg, i, i + j, (i & k) == 0);
+      }
+    }
+  }
+  __syncthreads();
+  double* cu = coords + d.coord_off;
+  double* cv = cu + n;
+  for (int i = threadIdx.x; i < n; i += kBatchSortThreads) {
+    const uint64_t g = sg[i];
+    cu[i] = (double)(sm_output(skey, 2 * g) >> 11) * 0x1.0p-53;
+    cv[i] = (double)(sm_output(skey, 2 * g + 1) >> 11) * 0x1.0p-53;
+  }
+}
+
 }  // namespace
 
 size_t sprinkle_ws_bytes(int region, int64_t n) { return layout(region, n, nullptr, nullptr); }
@@ -386,6 +431,15 @@ cs_status launch_sprinkle(int region, double eta0, uint64_t seed, int64_t n, dou
   if (s != CS_OK) return s;
   hipLaunchKernelGGL(k_gather, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, st, w.raw,
                      w.gens, planes, n, coords);
+  CS_LAUNCH_CHECK();
+  return CS_OK;
+}
+
+cs_status launch_sprinkle_batch(const uint64_t* seeds, const BatchInst* inst, int64_t count,
+                                double* coords, hipStream_t st) {
+  if (count <= 0) return CS_OK;
+  hipLaunchKernelGGL(k_sprinkle_mink2_batch, dim3((unsigned)count), dim3(kBatchSortThreads), 0, st,
+                     seeds, inst, coords);
   CS_LAUNCH_CHECK();
   return CS_OK;
 }

@@ -1,0 +1,116 @@
+"""GPU parity of the ensemble path: per-instance N_n bit-exact and actions within 1e-12
+of the oracle's pipeline on each instance; both counters, both MFMA tile shapes, the
+HIP-graph replay, and the 256-instance workload (sampled instances)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SIZES = [2, 3, 64, 100, 513, 1024, 2048, 3000, 4095, 4096, 5000, 8192]
+EPS = (0.0, 0.1, 0.2)
+
+
+@pytest.fixture(scope="module")
+def cs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_04463_amd as cs
+    cs.lib()
+    return cs
+
+
+def run_batch(cs, sizes, seeds, counter, tune_cache=None):
+    plan = cs.BatchPlan(sizes, counter=counter, eps=EPS, tune_cache=tune_cache)
+    dev = torch.device("cuda")
+    s = torch.from_numpy(np.asarray(seeds, dtype=np.uint64).view(np.int64)).to(dev)
+    hist = torch.empty(plan.hist_len, dtype=torch.int64, device=dev)
+    acts = torch.empty(len(sizes) * len(EPS), dtype=torch.float64, device=dev)
+    ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=dev)
+    plan.run(s, hist, acts, ws)
+    torch.cuda.synchronize()
+    return plan, hist.cpu().numpy().view(np.uint64).copy(), acts.cpu().numpy().copy()
+
+
+def check_instances(orc, plan, hist, acts, sizes, seeds, which):
+    for k in which:
+        n = int(sizes[k])
+        _, _, h, a = orc.pipeline(W.MINK2_DIAMOND, n, int(seeds[k]), eps_list=EPS[1:], fast=True)
+        off = plan.offsets[k]
+        assert np.array_equal(hist[off:off + n - 1], h), (k, n)
+        for e, eps in enumerate(EPS):
+            got, want = acts[k * len(EPS) + e], a[eps]
+            assert abs(got - want) <= 1e-12 * abs(want), (k, n, eps, got, want)
+
+
+@pytest.mark.parametrize("counter", [0, 1], ids=["bitset", "mfma"])
+def test_batch_mixed_sizes(cs, orc, counter):
+    seeds = [1000 + 17 * k for k in range(len(SIZES))]
+    plan, hist, acts = run_batch(cs, SIZES, seeds, counter)
+    check_instances(orc, plan, hist, acts, SIZES, seeds, range(len(SIZES)))
+
+
+@pytest.mark.parametrize("thr", [2, 100000], ids=["all256", "all128"])
+def test_batch_tile_shapes(cs, orc, tmp_path, thr):
+    cache = tmp_path / "tune.json"
+    cache.write_text(json.dumps({"tile256_min_n": thr}))
+    sizes = [130, 700, 2500, 4100, 8000]
+    seeds = [77, 78, 79, 80, 81]
+    plan, hist, acts = run_batch(cs, sizes, seeds, 1, tune_cache=str(cache))
+    check_instances(orc, plan, hist, acts, sizes, seeds, range(len(sizes)))
+
+
+def test_batch_graph_replays(cs, orc):
+    sizes = [300, 1500, 4200, 6000, 999]
+    seeds = [5, 6, 7, 8, 9]
+    dev = torch.device("cuda")
+    plan = cs.BatchPlan(sizes, counter=1, eps=EPS)
+    s = torch.from_numpy(np.asarray(seeds, dtype=np.uint64).view(np.int64)).to(dev)
+    hist = torch.empty(plan.hist_len, dtype=torch.int64, device=dev)
+    acts = torch.empty(len(sizes) * len(EPS), dtype=torch.float64, device=dev)
+    ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=dev)
+    plan.run(s, hist, acts, ws)
+    torch.cuda.synchronize()
+    h0, a0 = hist.clone(), acts.clone()
+    g = plan.graph(s, hist, acts, ws)
+    for rep in range(4):
+        hist.fill_(-1)
+        acts.fill_(float("nan"))
+        x = torch.randn(1024, device=dev).sum()  # eager work between replays
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(hist, h0), rep
+        assert torch.equal(acts, a0), rep
+        del x
+    check_instances(orc, plan, h0.cpu().numpy().view(np.uint64), a0.cpu().numpy(), sizes, seeds,
+                    range(len(sizes)))
+
+
+def test_batch_workload_256(cs, orc):
+    cfg = W.WORKLOADS["batch_mink2_256"]
+    sizes, seeds = W.batch_instances(cfg["seed"], cfg["count"], cfg["nmin"], cfg["nmax"])
+    plan, hist, acts = run_batch(cs, sizes, seeds, 1)
+    rng = np.random.default_rng(0)
+    which = sorted(set(rng.choice(len(sizes), 6, replace=False).tolist()
+                       + [int(np.argmax(sizes)), int(np.argmin(sizes))]))
+    check_instances(orc, plan, hist, acts, sizes, seeds, which)
+    # every instance: ordering fraction 1/2 within 6 standard deviations (sd ~ 1/sqrt(n)/3)
+    for k, n in enumerate(sizes):
+        off = plan.offsets[k]
+        R = int(hist[off:off + n - 1].sum())
+        assert abs(R / (n * (n - 1) / 2) - 0.5) < 6 * 0.6 / np.sqrt(n), (k, n, R)
+
+
+def test_autotune_writes_cache(cs, tmp_path):
+    path = tmp_path / "tune.json"
+    cs.cs_autotune(str(path))
+    torch.cuda.synchronize()
+    d = json.loads(path.read_text())
+    assert d["tile256_min_n"] >= 512 and len(d["ms"]) == 8
+    assert all(m["tile128"] > 0 and m["tile256"] > 0 for m in d["ms"])

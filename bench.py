@@ -32,8 +32,11 @@ if ROOT not in sys.path:
 
 import workloads as W  # noqa: E402
 
-PEAK_INT8_OPS = 5.0e15
+PEAK_INT8_OPS = 5.0e15   # MI355X dense int8 MFMA
+PEAK_FP4_OPS = 10.1e15   # MI355X dense fp4 MFMA
 PEAK_VALU_BITPAIRS = 256 * 4 * 16 * 2.4e9 * 16  # 2 VALU ops per 32 bit-pairs (AND, BCNT)
+COUNTERS = {"bitset": 0, "mfma": 1, "mfma_fp4": 2}
+PEAKS = {"mfma": (PEAK_INT8_OPS, "int8"), "mfma_fp4": (PEAK_FP4_OPS, "fp4")}
 
 
 def parse():
@@ -43,16 +46,36 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="mink4_n131072", choices=sorted(
         k for k in W.WORKLOADS if not k.startswith("batch")))
-    ap.add_argument("--no-bitset", action="store_true")
+    ap.add_argument("--counter", default="mfma", choices=["mfma", "mfma_fp4"],
+                    help="interval counter used in the timed step")
+    ap.add_argument("--no-bitset", action="store_true",
+                    help="skip the side legs (the other two counters)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU work for the oracle sample")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB, a kernel of "
+                         "known traffic for scaling HBM counters (FETCH_SIZE, WRITE_SIZE)")
     return ap.parse_args()
 
 
 def events_ms(pairs):
     return [a.elapsed_time(b) for a, b in pairs]
+
+
+def measured_traffic(kernel_source: str, summary: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, or None when the
+    kernel source has changed since the counters were taken (hash mismatch)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(os.path.join(ROOT, kernel_source), "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def main():
@@ -82,8 +105,18 @@ def main():
     acts = torch.empty(1 + len(eps_list), dtype=torch.float64, device=dev)
     sp_ws = torch.empty(L.cs_sprinkle_workspace_bytes(region, n), dtype=torch.uint8, device=dev)
     hist_ws = {c: torch.empty(L.cs_histogram_workspace_bytes(n, c), dtype=torch.uint8, device=dev)
-               for c in (cs.CS_COUNT_MFMA, cs.CS_COUNT_BITSET)}
+               for c in COUNTERS.values()}
+    main = COUNTERS[args.counter]
     eta0 = W.DS_ETA0
+
+    if args.copy_calibration_mb > 0:
+        nb = args.copy_calibration_mb << 20
+        src = torch.ones(nb // 8, dtype=torch.int64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(counter, ev=None):
         sp_coords = coords
@@ -102,13 +135,13 @@ def main():
             cs.cs_action(hist, n, dim, e, out=acts[k + 1:k + 2], stream=stream)
 
     for _ in range(args.warmup):
-        step(cs.CS_COUNT_MFMA)
+        step(main)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(cs.CS_COUNT_MFMA, evs[k])
+        step(main, evs[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
@@ -118,6 +151,8 @@ def main():
     useful_macs = n * (n - 1) * (n - 2) // 6
     achieved = 2 * useful_macs / (np.mean(count_ms) * 1e-3)
     actions = acts.cpu().tolist()
+    peak, kind = PEAKS[args.counter]
+    kernel = "k_count_mfma<4, %s>" % ("true" if kind == "fp4" else "false")
 
     out = {
         "metric": "related-pair interval counts/sec (4D, N=131072), MFMA vs bitset; ensembles/sec",
@@ -130,36 +165,49 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8-mfma/int32 counts, fp64 coordinates and action",
+        "dtype": ("int8 MFMA with int32 accumulation" if kind == "int8" else
+                  "fp4 (e2m1 0/1) MFMA with f32 accumulation") +
+                 " (exact integer counts); fp64 coordinates and action",
         "data": "synthetic sprinkling (seeded counter-based SplitMix64), no dataset",
         "config": {"workload": args.workload, "region": W.REGION_NAMES[region], "n": n,
-                   "seed": seed, "eps": list(eps_list), "counter": "mfma"},
+                   "seed": seed, "eps": list(eps_list), "counter": args.counter},
         "relations": R,
         "count_kernel_ms": {"mean": float(np.mean(count_ms)), "min": float(np.min(count_ms))},
         "counts_per_s_kernel": R / (np.mean(count_ms) * 1e-3),
         "actions": {"local": actions[0], **{f"eps={e}": a for e, a in zip(eps_list, actions[1:])}},
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_INT8_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / PEAK_INT8_OPS, "traffic": None,
-                     "kernel": "k_count_mfma<4>",
-                     "work_per_launch": f"2*N(N-1)(N-2)/6 = {2 * useful_macs:.4e} int8 ops"},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic("paper_1805_04463_amd/csrc/count.hip",
+                                                 f"traffic_count_{args.counter}_mink4_n131072.json"),
+                     "kernel": kernel,
+                     "work_per_launch": f"2*N(N-1)(N-2)/6 = {2 * useful_macs:.4e} {kind} ops"},
     }
 
     if not args.no_bitset:
-        bev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(2)]
-        for k in range(2):
-            bev[k][0].record(stream)
-            cs.cs_interval_histogram(bits, n, cs.CS_COUNT_BITSET, out=hist,
-                                     workspace=hist_ws[cs.CS_COUNT_BITSET], stream=stream)
-            bev[k][1].record(stream)
-        torch.cuda.synchronize()
-        hb = hist.cpu().numpy().view(np.uint64)
-        bms = min(events_ms(bev))
-        out["bitset"] = {"count_kernel_ms": bms, "counts_per_s_kernel": R / (bms * 1e-3),
-                         "useful_bitpairs_per_s": useful_macs / (bms * 1e-3),
-                         "frac_valu_peak": useful_macs / (bms * 1e-3) / PEAK_VALU_BITPAIRS,
-                         "identical_to_mfma": bool(np.array_equal(hb, h)),
-                         "mfma_speedup": bms / float(np.min(count_ms))}
+        for name, c in COUNTERS.items():
+            if name == args.counter:
+                continue
+            bev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(2)]
+            for k in range(2):
+                bev[k][0].record(stream)
+                cs.cs_interval_histogram(bits, n, c, out=hist, workspace=hist_ws[c], stream=stream)
+                bev[k][1].record(stream)
+            torch.cuda.synchronize()
+            hb = hist.cpu().numpy().view(np.uint64)
+            bms = min(events_ms(bev))
+            leg = {"count_kernel_ms": bms, "counts_per_s_kernel": R / (bms * 1e-3),
+                   "identical_histogram": bool(np.array_equal(hb, h)),
+                   "time_vs_main_counter": bms / float(np.min(count_ms))}
+            if name == "bitset":
+                leg["useful_bitpairs_per_s"] = useful_macs / (bms * 1e-3)
+                leg["frac_valu_peak"] = useful_macs / (bms * 1e-3) / PEAK_VALU_BITPAIRS
+            else:
+                p, kd = PEAKS[name]
+                leg["achieved_TOPs"] = 2 * useful_macs / (bms * 1e-3) / 1e12
+                leg["frac_peak"] = 2 * useful_macs / (bms * 1e-3) / p
+                leg["peak_TOPs"] = p / 1e12
+            out[name] = leg
 
     if not args.no_batch and hasattr(L, "cs_batch_run"):
         from bench_batch import run_batch  # noqa: E402  (batch leg lives beside this file)
@@ -174,12 +222,14 @@ def main():
         b_np = oracle.causal_matrix(region, c_np)
         t_link = time.perf_counter() - tm
         del c_np
-        # Rows spread evenly over the set; pilot sample sizes the real one.
-        pilot = np.linspace(0, n - 2, 16).astype(np.int64)
+        # Rows spread evenly over the set; a pilot of 8 rows per thread sizes the sample
+        # so that the timed part takes about --cpu-seconds.
+        npilot = 8 * oracle.max_threads()
+        pilot = np.linspace(0, n - 2, npilot).astype(np.int64)
         tp = time.perf_counter()
-        _, pp = oracle.histogram_fast_rows(b_np, n, pilot)
+        oracle.histogram_fast_rows(b_np, n, pilot)
         tpil = time.perf_counter() - tp
-        nrows = int(np.clip(16 * args.cpu_seconds / max(tpil, 1e-3), 16, n - 1))
+        nrows = int(np.clip(npilot * args.cpu_seconds / max(tpil, 1e-3), npilot, n - 1))
         rows = np.linspace(0, n - 2, nrows).astype(np.int64)
         tc = time.perf_counter()
         _, pairs = oracle.histogram_fast_rows(b_np, n, rows)

@@ -62,10 +62,14 @@ typedef enum {
  * predicates are evaluated in IEEE fp64 in the order written, without contraction. */
 enum { CS_MINK2_DIAMOND = 0, CS_MINK4_DIAMOND = 1, CS_DS4_SLAB = 2 };
 
-/* Interval counters. */
+/* Interval counters (all three give identical, exact results). */
 enum {
-    CS_COUNT_BITSET = 0,  /* VALU: 32-bit AND + popcount over LDS-staged row words     */
-    CS_COUNT_MFMA = 1     /* dense C.C on int8 MFMA (v_mfma_i32_32x32x32_i8), int32 acc */
+    CS_COUNT_BITSET = 0,   /* VALU: 32-bit AND + popcount over LDS-staged row words      */
+    CS_COUNT_MFMA = 1,     /* dense C.C on int8 MFMA (v_mfma_i32_32x32x32_i8), int32 acc  */
+    CS_COUNT_MFMA_FP4 = 2  /* dense C.C on fp4 MFMA (v_mfma_scale_f32_32x32x64_f8f6f4,
+                              e2m1 operands 0 / 1.0, unit scales), f32 acc: exact because
+                              every product is 0 or 1 and counts stay below 2^24; needs
+                              n < 2^24 (CS_ERR_OVERFLOW otherwise)                        */
 };
 
 /* Number of fp64 coordinate planes of a region (2, 4 or 7); -1 if unknown. */
@@ -111,7 +115,7 @@ size_t cs_histogram_workspace_bytes(int64_t n, int counter);
  * Interval abundances: hist[m] = N_m = number of pairs i < j with i ≺ j and exactly m
  * elements k with i ≺ k ≺ j, for m = 0 .. n-2 (the thesis's n_{m+1}).
  *   bits     device, the matrix from cs_causal_matrix (n rows, ld_words stride).
- *   counter  CS_COUNT_BITSET or CS_COUNT_MFMA; both give identical results.
+ *   counter  CS_COUNT_BITSET, CS_COUNT_MFMA or CS_COUNT_MFMA_FP4; identical results.
  *   hist     device, n-1 uint64, overwritten (zeroed by the callee).
  *   workspace device, at least cs_histogram_workspace_bytes(n, counter) bytes.
  */

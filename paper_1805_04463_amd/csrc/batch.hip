@@ -4,9 +4,10 @@
 //
 // Plan: per-instance offsets into three concatenated buffers (coordinates, matrices,
 // histograms), the builder's work list (one item per 64x64 block pair bi <= bj) and
-// the counters' work lists (one item per output tile I <= J), sorted longest K-range
-// first across all instances so the persistent counter balances instances of very
-// different sizes.  These tables live in device memory owned by the plan, uploaded
+// the counters' work lists (one item per row panel I of output tiles, i.e. all tiles
+// (I, J >= I) of an instance, so a workgroup keeps one instance's histogram in LDS for
+// a whole panel), sorted by cost across all instances so the persistent counter
+// balances instances of very different sizes.  These tables live in device memory owned by the plan, uploaded
 // once at plan time, so a run only enqueues kernels: fill, sprinkle, build, count
 // (one persistent launch per tile shape in use), action.
 //
@@ -98,9 +99,8 @@ cs_status build_plan(int64_t count, const int64_t* n, int counter, int n_eps, co
     int slot = counter == CS_COUNT_BITSET ? 0 : (d.n >= tile256_min_n ? 2 : 1);
     const int64_t BM = slot == 2 ? 256 : 128;
     const int64_t T = ceil_div(d.n, BM);
-    for (int64_t I = 0; I < T; ++I)
-      for (int64_t J = I; J < T; ++J)
-        items[slot].push_back({(uint32_t)(k << 16 | I << 8 | J), (J - I + 1) * BM * BM * BM});
+    for (int64_t I = 0; I < T; ++I)  // row panel I: tiles (I, J) for J = I .. T-1
+      items[slot].push_back({(uint32_t)(k << 16 | I << 8), (T - I) * (T - I + 1) / 2 * BM * BM * BM});
   }
   p->coords_len = coff;
   p->bits_len = boff;
@@ -149,8 +149,8 @@ cs_status run_counts(cs_batch_plan_t* p, const uint64_t* bits, uint64_t* hist, u
                      hipStream_t st) {
   for (int s = 0; s < 3; ++s) {
     if (!p->n_items[s]) continue;
-    cs_status r = launch_count_batch(kModeOf[s], bits, p->d_inst, p->d_items[s], p->n_items[s],
-                                     hist, ctr + s, st);
+    cs_status r = launch_count_batch(kModeOf[s], p->counter == CS_COUNT_MFMA_FP4, bits, p->d_inst,
+                                     p->d_items[s], p->n_items[s], hist, ctr + s, st);
     if (r != CS_OK) return r;
   }
   return CS_OK;
@@ -164,7 +164,8 @@ cs_status cs_batch_plan(int64_t count, const int64_t* n, int counter, int n_eps,
                         const char* tune_cache, cs_batch_plan_handle* plan) {
   if (!plan) return CS_ERR_INVALID_ARG;
   *plan = nullptr;
-  if (counter != CS_COUNT_BITSET && counter != CS_COUNT_MFMA) return CS_ERR_UNSUPPORTED;
+  if (counter != CS_COUNT_BITSET && counter != CS_COUNT_MFMA && counter != CS_COUNT_MFMA_FP4)
+    return CS_ERR_UNSUPPORTED;
   if (count < 1 || count > 65535 || !n || n_eps < 0 || (n_eps > 0 && !eps))
     return CS_ERR_INVALID_ARG;
   for (int64_t k = 0; k < count; ++k)

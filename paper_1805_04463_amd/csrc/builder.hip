@@ -3,15 +3,12 @@
 // sorted DAG kept as P + P^T; Ch. 4: i ≺ j iff timelike separated).
 //
 // Work decomposition: one wave per 64x64 block (bi <= bj) of the upper triangle.
-// Lane l owns column j = 64*bj + l (coordinates in registers); the wave walks the
-// 64 rows i of block bi with i's coordinates as wave-uniform (scalar) operands.
-// Each predicate is evaluated once per unordered pair:
-//   - the wave ballot over lanes is row i's 64-bit word for column block bj;
-//   - each lane ORs bit (i - 64*bi) into its own register, which after the loop is
-//     row j's word for column block bi (the transposed word), so no second pass.
-// Both words are then stored by the lanes that own them.  Four waves of a workgroup
-// take four consecutive column blocks of the same row block, so each row i receives
-// 32 contiguous bytes from one workgroup.
+// Lane l owns row i = 64*bi + l (coordinates in registers) and tests it against the
+// 64 column points of block bj, which the wave stages in LDS and reads back as
+// broadcasts; its 64 answers form row i's word for column block bj.  A 64x64 bit
+// transpose across the wave (six butterfly stages of lane shuffles) turns those row
+// words into the words of rows j for column block bi, so each unordered pair is tested
+// once and both halves of the symmetric matrix are written.
 //
 // Arithmetic: fp64, in the order written, no contraction (built with
 // -ffp-contract=off and explicit round-to-nearest intrinsics); on CDNA4 fp64 VALU
@@ -51,7 +48,7 @@ __device__ inline Pt<CS_DS4_SLAB> load_pt(const double* c, int64_t n, int64_t i,
 
 // a ≺ b for a earlier than b in time order.
 __device__ inline bool precedes(const Pt<CS_MINK2_DIAMOND>& a, const Pt<CS_MINK2_DIAMOND>& b) {
-  return a.u < b.u && a.v < b.v;
+  return (a.u < b.u) & (a.v < b.v);
 }
 __device__ inline bool precedes(const Pt<CS_MINK4_DIAMOND>& a, const Pt<CS_MINK4_DIAMOND>& b) {
   double dt = __dsub_rn(b.t, a.t);
@@ -60,7 +57,7 @@ __device__ inline bool precedes(const Pt<CS_MINK4_DIAMOND>& a, const Pt<CS_MINK4
   double dz = __dsub_rn(b.z, a.z);
   double s = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
   s = __dadd_rn(s, __dmul_rn(dz, dz));
-  return dt > 0.0 && __dmul_rn(dt, dt) > s;
+  return (dt > 0.0) & (__dmul_rn(dt, dt) > s);
 }
 __device__ inline bool precedes(const Pt<CS_DS4_SLAB>& a, const Pt<CS_DS4_SLAB>& b) {
   // eta_a < eta_b and cos(eta_b - eta_a) < n_a . n_b (both angles in [0, pi]).
@@ -68,51 +65,79 @@ __device__ inline bool precedes(const Pt<CS_DS4_SLAB>& a, const Pt<CS_DS4_SLAB>&
   double dot = __dadd_rn(__dmul_rn(a.n0, b.n0), __dmul_rn(a.n1, b.n1));
   dot = __dadd_rn(dot, __dmul_rn(a.n2, b.n2));
   dot = __dadd_rn(dot, __dmul_rn(a.n3, b.n3));
-  return a.x < b.x && cd < dot;
+  return (a.x < b.x) & (cd < dot);
 }
 
 constexpr int kWavesPerBlock = 4;
 
+// 64x64 bit transpose across a wave: lane l holds word x with bit c = element (l, c);
+// afterwards lane c holds bit l = element (l, c).  Six butterfly stages; at stage s the
+// off-diagonal s x s sub-blocks are swapped with the partner lane l ^ s.
+__device__ inline uint64_t wave_transpose64(uint64_t x) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lo_masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull,
+                                0x00FF00FF00FF00FFull, 0x0F0F0F0F0F0F0F0Full,
+                                0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int s = 32 >> k;
+    const uint64_t mlo = lo_masks[k], mhi = ~mlo;
+    const uint32_t ylo = (uint32_t)__shfl_xor((int)(uint32_t)x, s);
+    const uint32_t yhi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), s);
+    const uint64_t y = ((uint64_t)yhi << 32) | ylo;
+    x = (lane & s) ? ((x & mhi) | ((y & mhi) >> s)) : ((x & mlo) | ((y & mlo) << s));
+  }
+  return x;
+}
+
 // One wave: the 64x64 block (bi, bj), bi <= bj, of an n-point matrix S with stride ld.
-// The wave owning the last column block of a row block also zeroes that row block's
-// padding words [nb, ld), so every word of S is written exactly once.
+// Lane l owns row i = 64 bi + l; the 64 column points are staged in LDS by the wave
+// and read back as broadcasts, and lane l collects its row word bit by bit.  The
+// transposed words (rows of block bj, columns of block bi) come from one 64x64 bit
+// transpose of the row words, so each unordered pair is tested once.  The wave
+// owning the last column block of a row block also zeroes that row block's padding
+// words [nb, ld), so every word of S is written exactly once.
 template <int R>
 __device__ inline void build_block(const double* __restrict__ coords, int64_t n,
                                    uint64_t* __restrict__ S, int64_t ld, int64_t nb, int64_t bi,
-                                   int64_t bj) {
+                                   int64_t bj, Pt<R>* cols) {
   const int lane = threadIdx.x & 63;
-  const int64_t j = bj * 64 + lane;
-  const bool jv = j < n;
-  Pt<R> pj = load_pt(coords, n, jv ? j : n - 1, (Pt<R>*)nullptr);
-  const int64_t i0 = bi * 64;
-  const int rows = (int)(n - i0 < 64 ? n - i0 : 64);
-  uint64_t rowword = 0, colword = 0;
-  for (int r = 0; r < rows; ++r) {
-    const int64_t i = i0 + r;
-    Pt<R> pi = load_pt(coords, n, i, (Pt<R>*)nullptr);
-    const bool rel = jv && i < j && precedes(pi, pj);
-    const uint64_t m = __ballot(rel);
-    if (lane == r) rowword = m;
-    if (rel) colword |= 1ull << r;
-  }
-  const int64_t irow = i0 + lane;
+  const int64_t i = bi * 64 + lane, j = bj * 64 + lane;
+  const bool iv = i < n, jv = j < n;
+  const Pt<R> pi = load_pt(coords, n, iv ? i : n - 1, (Pt<R>*)nullptr);
+  cols[lane] = load_pt(coords, n, jv ? j : n - 1, (Pt<R>*)nullptr);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the wave's LDS writes have landed
+  __builtin_amdgcn_wave_barrier();
+  uint32_t lo = 0, hi = 0;
+#pragma unroll
+  for (int c = 0; c < 32; ++c) lo |= (uint32_t)precedes(pi, cols[c]) << c;
+#pragma unroll
+  for (int c = 0; c < 32; ++c) hi |= (uint32_t)precedes(pi, cols[32 + c]) << c;
+  __builtin_amdgcn_wave_barrier();
+  const int64_t ncols = n - bj * 64;  // valid columns of this block (>= 1)
+  uint64_t row = ((uint64_t)hi << 32) | lo;
+  if (ncols < 64) row &= (1ull << ncols) - 1ull;
+  if (bi == bj) row &= lane == 63 ? 0ull : (~0ull << (lane + 1));  // only j > i
+  if (!iv) row = 0;
+  const uint64_t col = wave_transpose64(row);  // lane l: row j's bits for columns of bi
   if (bi == bj) {
-    if (irow < n) S[irow * ld + bi] = rowword | colword;
+    if (iv) S[i * ld + bi] = row | col;
   } else {
-    if (irow < n) S[irow * ld + bj] = rowword;
-    if (jv) S[j * ld + bi] = colword;
+    if (iv) S[i * ld + bj] = row;
+    if (jv) S[j * ld + bi] = col;
   }
-  if (bj == nb - 1 && irow < n)
-    for (int64_t w = nb; w < ld; ++w) S[irow * ld + w] = 0;
+  if (bj == nb - 1 && iv)
+    for (int64_t w = nb; w < ld; ++w) S[i * ld + w] = 0;
 }
 
 template <int R>
 __global__ __launch_bounds__(256) void k_build(const double* __restrict__ coords, int64_t n,
                                                uint64_t* __restrict__ S, int64_t ld, int64_t nb) {
+  __shared__ Pt<R> cols[kWavesPerBlock][64];
   const int64_t bi = blockIdx.y;
   const int64_t bj = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (bj >= nb || bj < bi) return;  // wave-uniform exit; no barriers
-  build_block<R>(coords, n, S, ld, nb, bi, bj);
+  if (bj >= nb || bj < bi) return;  // wave-uniform exit; no block barriers below
+  build_block<R>(coords, n, S, ld, nb, bi, bj, cols[threadIdx.x >> 6]);
 }
 
 // Ensemble of 1+1 diamonds: wave w of block b takes work item 4b + w, packed as
@@ -121,12 +146,14 @@ __global__ __launch_bounds__(256) void k_build_batch(const double* __restrict__ 
                                                      const BatchInst* __restrict__ inst,
                                                      const uint32_t* __restrict__ items,
                                                      int64_t nitems, uint64_t* __restrict__ bits) {
+  __shared__ Pt<CS_MINK2_DIAMOND> cols[kWavesPerBlock][64];
   const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (t >= nitems) return;
   const uint32_t it = items[t];
   const BatchInst d = inst[it >> 16];
   build_block<CS_MINK2_DIAMOND>(coords + d.coord_off, d.n, bits + d.bits_off, d.ld,
-                                ceil_div(d.n, 64), (it >> 8) & 255u, it & 255u);
+                                ceil_div(d.n, 64), (it >> 8) & 255u, it & 255u,
+                                cols[threadIdx.x >> 6]);
 }
 
 template <int R>

@@ -107,8 +107,9 @@ cs_status launch_sprinkle_batch(const uint64_t* seeds, const BatchInst* inst, in
 cs_status launch_build_batch(const double* coords, const BatchInst* inst,
                              const uint32_t* items, int64_t nitems, uint64_t* bits,
                              hipStream_t st);
-// mode 0: bitset counter (128 tiles); 2 / 4: MFMA counter with 128 / 256 tiles.
-cs_status launch_count_batch(int mode, const uint64_t* bits, const BatchInst* inst,
+// mode 0: bitset counter (128 tiles); 2 / 4: MFMA counter with 128 / 256 tiles, on the
+// int8 or (fp4 = true) the fp4 matrix cores.
+cs_status launch_count_batch(int mode, bool fp4, const uint64_t* bits, const BatchInst* inst,
                              const uint32_t* items, int64_t nitems, uint64_t* hist,
                              unsigned int* counter, hipStream_t st);
 cs_status launch_action_batch(const uint64_t* hist, const BatchInst* inst, int64_t count,

@@ -14,12 +14,17 @@
 //     K-range first (tiles with the same distance J - I from the diagonal have
 //     equal cost);
 //   - a whole-tile skip when no pair of the tile is related;
-//   - K staged through LDS 256 bits at a time with register prefetch of the next
-//     stage; the triangular masks (k > i for A, k < j for B) are applied while
-//     staging;
+//   - K staged through LDS 256 bits at a time; the triangular masks (k > i for A,
+//     k < j for B) only matter on stages that overlap the tile's own diagonal
+//     blocks and are applied only there;
 //   - an epilogue that tests the related bit S[j][i] of each output and bins the
-//     count into a per-workgroup LDS histogram (16384 uint32 bins) or, beyond it,
+//     count into a per-workgroup LDS histogram (HB uint32 bins) or, beyond it,
 //     straight into the global uint64 histogram; LDS bins are flushed at exit.
+// The MFMA counter fills a 4-deep LDS ring with direct global->LDS DMA loads
+// (buffer_load_dwordx4 ... lds; rows past n read as zero through the buffer
+// descriptor's range), so three stages are in flight while one is multiplied and
+// each stage costs one barrier.  The bitset counter prefetches one stage through
+// registers.
 // They differ in the inner product:
 //   MFMA   bits are expanded to int8 0/1 in registers and multiplied on
 //          v_mfma_i32_32x32x32_i8 with int32 accumulation (exact: counts < 2^31).
@@ -28,6 +33,8 @@
 //          byte b of register q = bit (4h + q + 8b) of the word (h = lane >> 5),
 //          costs two VALU ops per four bytes.
 //   BITSET AND + v_bcnt_u32_b32 on 32-bit words, each thread an 8x8 block of pairs.
+#include <type_traits>
+
 #include "common.h"
 
 namespace cs {
@@ -39,7 +46,8 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kThreads = 256;
 constexpr int kStageBits = 256;         // K bits per LDS stage
 constexpr int kStageWords = kStageBits / 32;
-constexpr int kLdsBins = 16384;         // per-workgroup histogram bins (uint32)
+constexpr int kBinsSingle = 8192;       // LDS histogram bins, single instance (32 KiB)
+constexpr int kBinsBatch = 8192;        // LDS histogram bins, ensembles (n <= 8192)
 
 // Output tile t (0-based) in longest-first order for a T x T tile triangle:
 // e = T-1-(J-I) is the diagonal rank, tiles with the same e are consecutive.
@@ -61,6 +69,14 @@ __device__ inline uint32_t mask_below(int64_t kw, int64_t g) {
   if (kw + 32 <= g) return 0xFFFFFFFFu;
   if (kw >= g) return 0u;
   return (1u << (uint32_t)(g - kw)) - 1u;
+}
+
+// The same masks from the offset d = kw - g (fits 32 bits inside a tile).
+__device__ inline uint32_t mask_above_d(int32_t d) {
+  return d > 0 ? 0xFFFFFFFFu : (d <= -31 ? 0u : 0xFFFFFFFFu << (uint32_t)(1 - d));
+}
+__device__ inline uint32_t mask_below_d(int32_t d) {
+  return d <= -32 ? 0xFFFFFFFFu : (d >= 0 ? 0u : (1u << (uint32_t)(-d)) - 1u);
 }
 
 // LDS position (in uint32) of the 16-byte half `h` of staged row r: rows are 8
@@ -125,9 +141,10 @@ struct Stage {
 
 // Counts are at most n-2 by construction; the bound check keeps a histogram write in
 // range whatever the inputs.  `tmax` tracks the largest LDS bin this thread touched.
+template <int HB>
 __device__ inline void bin_add(uint32_t* lds_hist, unsigned long long* hist, uint32_t bin,
                                int64_t nbins, uint32_t& tmax) {
-  if (bin < (uint32_t)kLdsBins) {
+  if (bin < (uint32_t)HB) {
     atomicAdd(lds_hist + bin, 1u);
     tmax = bin > tmax ? bin : tmax;
   } else if ((int64_t)bin < nbins) {
@@ -136,6 +153,7 @@ __device__ inline void bin_add(uint32_t* lds_hist, unsigned long long* hist, uin
 }
 
 // Adds the LDS bins [0, max touched] to the global histogram and clears them.
+template <int HB>
 __device__ inline void flush_hist(uint32_t* lds_hist, unsigned long long* hist, int64_t nbins,
                                   uint32_t& tmax, uint32_t* s_max) {
   __syncthreads();
@@ -145,7 +163,7 @@ __device__ inline void flush_hist(uint32_t* lds_hist, unsigned long long* hist, 
   __syncthreads();
   int64_t lim = (int64_t)*s_max + 1;
   lim = lim < nbins ? lim : nbins;
-  lim = lim < kLdsBins ? lim : kLdsBins;
+  lim = lim < HB ? lim : HB;
   for (int b = threadIdx.x; b < lim; b += kThreads) {
     uint32_t v = lds_hist[b];
     if (v) {
@@ -178,93 +196,271 @@ struct TileArgs {
 // 32x32 outputs (WM = 4: 256x256 tile, 128x128 per wave, 256 int32 accumulators).
 // Returns false (having done nothing) when no pair of the tile is related.
 // ===========================================================================
+
+// s_waitcnt with vmcnt = N and no wait on the other counters (gfx9 encoding).
+template <int N>
+__device__ inline void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// MFMA stages: 512 bits of K = 64 contiguous bytes of every panel row, so each DMA
+// request covers half a 128-byte line and a line is consumed by two neighbouring
+// stages.  Within a stage, row r's four 16-byte chunks sit at positions c ^ (r/4 mod 4)
+// so that sixteen consecutive rows reading the same chunk hit distinct banks.
+constexpr int kMStageBits = 512;
+constexpr int kMStageU32 = kMStageBits / 32;  // uint32 words per row per stage
+// Stages in the LDS ring: three for 256-row panels (one workgroup per CU), two for
+// 128-row panels so that two workgroups fit in a CU's LDS.
+template <int BM>
+struct MRing {
+  static constexpr int value = BM == 256 ? 3 : 2;
+};
+
+__device__ inline int mpos(int r, int c) { return r * kMStageU32 + ((c ^ ((r >> 2) & 3)) << 2); }
+
+// One stage of a BM-row panel into an LDS stage buffer by DMA: thread t issues
+// BM*4/256 loads of 16 bytes; issue q of wave w writes slots q*256 + 64w + lane,
+// slot s = 4r + (c ^ (r/4 mod 4)).
+template <int BM>
+__device__ inline void dma_stage(__amdgpu_buffer_rsrc_t rsrc, uint32_t lds_stage_addr,
+                                 const int32_t* voff_row, int32_t kbyte) {
+  constexpr int kPer = BM * 4 / kThreads;
+  const uint32_t wave_off = __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) * 64 * 16);
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int32_t vo = voff_row[q] < 0 ? (int32_t)0x80000000 : voff_row[q] + kbyte;
+    const uint32_t lds_addr = lds_stage_addr + wave_off + q * kThreads * 16;
+    // Issued as inline assembly so the compiler does not add its own wait for the DMA
+    // before every LDS read; completion is tracked explicitly with wait_vmcnt.
+    asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
+                 :
+                 : "s"(lds_addr), "v"(vo), "s"(rsrc)
+                 : "memory", "m0");
+  }
+}
+
+// Panel byte offsets (row part + chunk) of this thread's DMA slots; -1 marks rows >= n.
+template <int BM>
+__device__ inline void dma_offsets(int32_t* voff_row, int64_t ld, int64_t valid_rows) {
+  constexpr int kPer = BM * 4 / kThreads;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int slot = q * kThreads + threadIdx.x;
+    const int r = slot >> 2;
+    const int c = (slot & 3) ^ ((r >> 2) & 3);
+    voff_row[q] = r < valid_rows ? (int32_t)(r * ld * 8 + c * 16) : -1;
+  }
+}
+
+__device__ inline v4i unpack_i8(uint32_t x, uint32_t sh) {
+  return (v4i){(int)((x >> sh) & 0x01010101u), (int)((x >> (sh + 1)) & 0x01010101u),
+               (int)((x >> (sh + 2)) & 0x01010101u), (int)((x >> (sh + 3)) & 0x01010101u)};
+}
+
+__device__ inline uint32_t word_of(const uint4& v, int w) {
+  return w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w;
+}
+
+// Bits S[j][i] for rows i in [rb + 32 mb, +32) of column j = J0 + 32 (WM wc + nb) + l32,
+// restricted to i < j (so only related pairs of the upper triangle remain).
 template <int WM>
-__device__ inline bool mfma_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs,
-                                 uint32_t* lds_hist, uint32_t& tmax) {
+__device__ inline uint32_t related_word(const TileArgs& ta, int64_t rb, int mb, int wc, int nb,
+                                        int l32) {
+  const int64_t j = ta.J0 + wc * (WM * 32) + nb * 32 + l32;
+  if (j >= ta.n) return 0u;
+  const int64_t i0 = rb + mb * 32;
+  return ta.S32[j * ta.ld32 + (i0 >> 5)] & mask_below(i0, j);
+}
+
+// The same 128 bits of K on the fp4 matrix cores (v_mfma_scale_f32_32x32x64_f8f6f4 with
+// both operands in e2m1, unit scales).  Each MFMA takes 64 k: lanes 0-31 take word 2u of
+// the chunk, lanes 32-63 word 2u+1.  Bit k becomes the e2m1 code 0b0010 (= 1.0) or 0
+// in nibble m of register q for k = q + 4m (a permutation of k shared by A and B), two
+// VALU ops per register.  Products are 0 or 1 and every count is below 2^24, so the
+// f32 accumulation is exact.
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ inline v8i unpack_fp4(uint32_t x) {
+  const uint32_t x2 = x << 1;
+  return (v8i){(int)(x2 & 0x22222222u), (int)((x >> 0) & 0x22222222u),
+               (int)((x >> 1) & 0x22222222u), (int)((x >> 2) & 0x22222222u), 0, 0, 0, 0};
+}
+
+// Triangular masks on a chunk: keep k > row for A words, k < row for B words.  da / db are
+// the offsets of the chunk's first bit from the lane's first A row / B row.
+template <int WM>
+__device__ inline void mask_chunk(uint4 (&aw)[WM], uint4 (&bw)[WM], int32_t da, int32_t db) {
+#pragma unroll
+  for (int mb = 0; mb < WM; ++mb) {
+    const int32_t d = da - mb * 32;
+    aw[mb].x &= mask_above_d(d);
+    aw[mb].y &= mask_above_d(d + 32);
+    aw[mb].z &= mask_above_d(d + 64);
+    aw[mb].w &= mask_above_d(d + 96);
+  }
+#pragma unroll
+  for (int nb = 0; nb < WM; ++nb) {
+    const int32_t d = db - nb * 32;
+    bw[nb].x &= mask_below_d(d);
+    bw[nb].y &= mask_below_d(d + 32);
+    bw[nb].z &= mask_below_d(d + 64);
+    bw[nb].w &= mask_below_d(d + 96);
+  }
+}
+
+// One stage (512 bits of K = 4 chunks of 128) as a flat, software-pipelined sequence of
+// k-steps: the operands of step t+1 are unpacked while the MFMAs of step t issue, and
+// the scheduler is told to interleave them (one MFMA, then a share of the VALU work), so
+// the matrix pipe is fed without bubbles and only two sets of operands are live.  The
+// LDS words of chunk c+1 are read while chunk c is multiplied.
+template <int WM, bool FP4>
+__device__ inline void mfma_stage(
+    typename std::conditional<FP4, v16f, v16i>::type (&acc)[WM][WM], const uint32_t* As,
+    const uint32_t* Bs, int arow, int brow, bool masked, int32_t da, int32_t db, uint32_t sh,
+    int hsel) {
+  constexpr int kSteps = FP4 ? 2 : 4;     // MFMA k-steps per 128-bit chunk
+  constexpr int kT = 4 * kSteps;          // k-steps per stage
+  using Frag = typename std::conditional<FP4, v8i, v4i>::type;
+  uint4 aw[2][WM], bw[2][WM];
+  Frag af[2][WM], bf[2][WM];
+  auto load_chunk = [&](int c, uint4 (&a)[WM], uint4 (&b)[WM]) {
+#pragma unroll
+    for (int mb = 0; mb < WM; ++mb) a[mb] = *(const uint4*)(As + mpos(arow + mb * 32, c));
+#pragma unroll
+    for (int nb = 0; nb < WM; ++nb) b[nb] = *(const uint4*)(Bs + mpos(brow + nb * 32, c));
+  };
+  auto unpack_step = [&](const uint4 (&a)[WM], const uint4 (&b)[WM], int w, Frag (&fa)[WM],
+                         Frag (&fb)[WM]) {
+#pragma unroll
+    for (int mb = 0; mb < WM; ++mb) {
+      if constexpr (FP4) fa[mb] = unpack_fp4(word_of(a[mb], 2 * w + hsel));
+      else fa[mb] = unpack_i8(word_of(a[mb], w), sh);
+    }
+#pragma unroll
+    for (int nb = 0; nb < WM; ++nb) {
+      if constexpr (FP4) fb[nb] = unpack_fp4(word_of(b[nb], 2 * w + hsel));
+      else fb[nb] = unpack_i8(word_of(b[nb], w), sh);
+    }
+  };
+  load_chunk(0, aw[0], bw[0]);
+  if (masked) mask_chunk<WM>(aw[0], bw[0], da, db);
+  unpack_step(aw[0], bw[0], 0, af[0], bf[0]);
+#pragma unroll
+  for (int t = 0; t < kT; ++t) {
+    const int c = t / kSteps, w = t % kSteps, cur = t & 1;
+    if (w == 0 && c + 1 < 4) load_chunk(c + 1, aw[(c + 1) & 1], bw[(c + 1) & 1]);
+    if (t + 1 < kT) {
+      const int cn = (t + 1) / kSteps, wn = (t + 1) % kSteps;
+      if (wn == 0 && masked) mask_chunk<WM>(aw[cn & 1], bw[cn & 1], da + cn * 128, db + cn * 128);
+      unpack_step(aw[cn & 1], bw[cn & 1], wn, af[cur ^ 1], bf[cur ^ 1]);
+    }
+#pragma unroll
+    for (int mb = 0; mb < WM; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < WM; ++nb) {
+        if constexpr (FP4)
+          acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+              af[cur][mb], bf[cur][nb], acc[mb][nb], 4, 4, 0, 127, 0, 127);
+        else
+          acc[mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[cur][mb], bf[cur][nb],
+                                                             acc[mb][nb], 0, 0, 0);
+      }
+    if (t + 1 < kT) {
+      // 2 WM unpacked registers of 4 (int8) per MFMA row/column: spread the next step's
+      // VALU work evenly between this step's WM*WM MFMAs.
+      constexpr int kValu = (FP4 ? 7 : 8) * 2 * WM / (WM * WM) + 1;
+#pragma unroll
+      for (int q = 0; q < WM * WM; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);      // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, kValu, 0);  // then VALU
+      }
+    }
+    // Keep each step's MFMAs in their own scheduling region: MFMAs of consecutive steps
+    // update the same accumulators and must not be placed back to back.
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int WM, int HB, bool FP4 = false>
+__device__ inline bool mfma_tile(const TileArgs& ta, uint32_t* ring, uint32_t* lds_hist,
+                                 uint32_t& tmax) {
+  using Acc = typename std::conditional<FP4, v16f, v16i>::type;
   constexpr int BM = 2 * WM * 32;
+  constexpr int kStage = BM * kMStageU32;      // one panel stage, uint32 words
+  constexpr int kPer = BM * 4 / kThreads;      // DMA loads per panel per thread
+  constexpr int kLoads = 2 * kPer;             // per stage (A and B)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int hsel = lane >> 5, l32 = lane & 31;
   const int64_t n = ta.n, I0 = ta.I0, J0 = ta.J0, nbins = n - 1;
   const int64_t rb = I0 + wr * (WM * 32);  // first output row of this wave
 
-  // Related bits S[j][i] for this wave's outputs: word mb of column block nb.
-  uint32_t relw[WM][WM];
+  // Skip the tile if none of its pairs is related.  The bit words are loaded again in
+  // the epilogue rather than kept live through the K loop.
   bool any = false;
 #pragma unroll
-  for (int nb = 0; nb < WM; ++nb) {
-    const int64_t j = J0 + wc * (WM * 32) + nb * 32 + l32;
+  for (int nb = 0; nb < WM; ++nb)
 #pragma unroll
-    for (int mb = 0; mb < WM; ++mb) {
-      uint32_t w = 0;
-      if (j < n) {
-        const int64_t i0 = rb + mb * 32;
-        w = ta.S32[j * ta.ld32 + (i0 >> 5)];
-        w &= mask_below(i0, j);  // only i < j
-      }
-      relw[nb][mb] = w;
-      any |= (w != 0);
-    }
-  }
+    for (int mb = 0; mb < WM; ++mb) any |= related_word<WM>(ta, rb, mb, wc, nb, l32) != 0;
   if (!__syncthreads_or(any)) return false;
 
-  v16i acc[WM][WM];
+  const int64_t ld = ta.ld32 >> 1;
+  const int64_t kbeg = I0;
+  const int64_t kend = (J0 + BM < n ? J0 + BM : n);
+  const int nst = (int)ceil_div(kend - kbeg, kMStageBits);
+  const int64_t va = n - I0 < BM ? n - I0 : BM, vb = n - J0 < BM ? n - J0 : BM;
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(ta.S32 + I0 * ta.ld32), (short)0, (int)(va * ld * 8), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rbf = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(ta.S32 + J0 * ta.ld32), (short)0, (int)(vb * ld * 8), 0x00020000);
+  int32_t oa[kPer], ob[kPer];
+  dma_offsets<BM>(oa, ld, va);
+  dma_offsets<BM>(ob, ld, vb);
+  const int32_t kbyte0 = (int32_t)(kbeg >> 3);
+
+  Acc acc[WM][WM];
 #pragma unroll
   for (int a = 0; a < WM; ++a)
 #pragma unroll
-    for (int b = 0; b < WM; ++b) acc[a][b] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < WM; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[a][b][e] = 0;
 
-  const int64_t kbeg = I0;
-  const int64_t kend = (J0 + BM < n ? J0 + BM : n);
-  const int64_t nst = ceil_div(kend - kbeg, kStageBits);
-  const int64_t row_bits = ta.ld32 * 32;
-  Stage<BM> sa, sb;
-  sa.init(ta.S32, ta.ld32, I0, n, kbeg);
-  sb.init(ta.S32, ta.ld32, J0, n, kbeg);
-  sa.fetch(0, kbeg, row_bits, I0, kbeg < I0 + BM, true);
-  sb.fetch(0, kbeg, row_bits, J0, kbeg + kStageBits > J0, false);
-  for (int64_t s = 0; s < nst; ++s) {
-    __syncthreads();
-    sa.store(As);
-    sb.store(Bs);
-    __syncthreads();
-    if (s + 1 < nst) {
-      const int64_t kb = kbeg + (s + 1) * kStageBits;
-      sa.fetch(s + 1, kb, row_bits, I0, kb < I0 + BM, true);
-      sb.fetch(s + 1, kb, row_bits, J0, kb + kStageBits > J0, false);
+  // LDS byte address of the ring (the low 32 bits of a generic LDS pointer).
+  const uint32_t ring_addr = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)ring);
+  constexpr int kMRing = MRing<BM>::value;
+#pragma unroll
+  for (int p = 0; p < kMRing - 1; ++p) {  // prologue: stages 0 .. kMRing-2 in flight
+    if (p < nst) {
+      const uint32_t st = ring_addr + p * 2 * kStage * 4;
+      dma_stage<BM>(ra, st, oa, kbyte0 + p * (kMStageBits / 8));
+      dma_stage<BM>(rbf, st + kStage * 4, ob, kbyte0 + p * (kMStageBits / 8));
     }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      uint4 aw[WM], bw[WM];
-#pragma unroll
-      for (int mb = 0; mb < WM; ++mb)
-        aw[mb] = *(const uint4*)(As + lds_pos(wr * WM * 32 + mb * 32 + l32, h));
-#pragma unroll
-      for (int nb = 0; nb < WM; ++nb)
-        bw[nb] = *(const uint4*)(Bs + lds_pos(wc * WM * 32 + nb * 32 + l32, h));
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        v4i af[WM], bf[WM];
-        const uint32_t sh = 4u * (uint32_t)hsel;
-#pragma unroll
-        for (int mb = 0; mb < WM; ++mb) {
-          const uint32_t x = w == 0 ? aw[mb].x : w == 1 ? aw[mb].y : w == 2 ? aw[mb].z : aw[mb].w;
-          af[mb] = (v4i){(int)((x >> sh) & 0x01010101u), (int)((x >> (sh + 1)) & 0x01010101u),
-                         (int)((x >> (sh + 2)) & 0x01010101u), (int)((x >> (sh + 3)) & 0x01010101u)};
-        }
-#pragma unroll
-        for (int nb = 0; nb < WM; ++nb) {
-          const uint32_t x = w == 0 ? bw[nb].x : w == 1 ? bw[nb].y : w == 2 ? bw[nb].z : bw[nb].w;
-          bf[nb] = (v4i){(int)((x >> sh) & 0x01010101u), (int)((x >> (sh + 1)) & 0x01010101u),
-                         (int)((x >> (sh + 2)) & 0x01010101u), (int)((x >> (sh + 3)) & 0x01010101u)};
-        }
-#pragma unroll
-        for (int mb = 0; mb < WM; ++mb)
-#pragma unroll
-          for (int nb = 0; nb < WM; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[mb], bf[nb], acc[mb][nb], 0, 0, 0);
-      }
+  }
+  const uint32_t sh = 4u * (uint32_t)hsel;
+  const int arow = wr * WM * 32 + l32, brow = wc * WM * 32 + l32;
+  const int32_t da0 = (int32_t)(kbeg - rb - l32);
+  const int32_t db0 = (int32_t)(kbeg - J0 - wc * (WM * 32) - l32);
+  for (int s = 0; s < nst; ++s) {
+    if (kMRing > 2 && s + 1 < nst) wait_vmcnt<kLoads>();  // stage s+1 may stay in flight
+    else wait_vmcnt<0>();
+    __syncthreads();  // stage s visible to all waves; all waves are done with stage s-1
+    if (s + kMRing - 1 < nst) {
+      const uint32_t st = ring_addr + ((s + kMRing - 1) % kMRing) * 2 * kStage * 4;
+      const int32_t kb = kbyte0 + (s + kMRing - 1) * (kMStageBits / 8);
+      dma_stage<BM>(ra, st, oa, kb);
+      dma_stage<BM>(rbf, st + kStage * 4, ob, kb);
     }
+    const uint32_t* As = ring + (s % kMRing) * 2 * kStage;
+    const uint32_t* Bs = As + kStage;
+    const int64_t kb = kbeg + (int64_t)s * kMStageBits;
+    const bool masked = kb < I0 + BM || kb + kMStageBits > J0;  // touches a diagonal block
+    const int32_t dst = da0 + s * kMStageBits, dbs = db0 + s * kMStageBits;
+    mfma_stage<WM, FP4>(acc, As, Bs, arow, brow, masked, dst, dbs, sh, hsel);
   }
 
   // Epilogue.  32x32 accumulator layout: lane holds column (lane & 31) and rows
@@ -273,12 +469,12 @@ __device__ inline bool mfma_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs,
   for (int nb = 0; nb < WM; ++nb) {
 #pragma unroll
     for (int mb = 0; mb < WM; ++mb) {
-      const uint32_t w = relw[nb][mb];
+      const uint32_t w = related_word<WM>(ta, rb, mb, wc, nb, l32);
       if (!w) continue;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int il = (e >> 2) * 8 + hsel * 4 + (e & 3);
-        if ((w >> il) & 1u) bin_add(lds_hist, ta.hist, (uint32_t)acc[mb][nb][e], nbins, tmax);
+        if ((w >> il) & 1u) bin_add<HB>(lds_hist, ta.hist, (uint32_t)acc[mb][nb][e], nbins, tmax);
       }
     }
   }
@@ -292,6 +488,7 @@ __device__ inline bool mfma_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs,
 // ===========================================================================
 constexpr int kBitsetTile = 128;
 
+template <int HB>
 __device__ inline bool bitset_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs,
                                    uint32_t* lds_hist, uint32_t& tmax) {
   constexpr int BM = kBitsetTile;
@@ -370,32 +567,39 @@ __device__ inline bool bitset_tile(const TileArgs& ta, uint32_t* As, uint32_t* B
   for (int a = 0; a < 8; ++a)
 #pragma unroll
     for (int b = 0; b < 8; ++b)
-      if ((rel[a] >> b) & 1u) bin_add(lds_hist, ta.hist, acc[a][b], nbins, tmax);
+      if ((rel[a] >> b) & 1u) bin_add<HB>(lds_hist, ta.hist, acc[a][b], nbins, tmax);
   return true;
 }
 
 // ===========================================================================
 // Single-instance kernels: persistent over the T(T+1)/2 tiles, longest first.
 // ===========================================================================
-template <int BM>
-struct TileLds {
-  uint32_t As[BM * kStageWords] __attribute__((aligned(16)));
-  uint32_t Bs[BM * kStageWords] __attribute__((aligned(16)));
-  uint32_t hist[kLdsBins];
+template <int BM, int HB>
+struct MfmaLds {
+  uint32_t ring[MRing<BM>::value * 2 * BM * kMStageU32] __attribute__((aligned(16)));
+  uint32_t hist[HB];
+  uint32_t maxbin;
+  int slot;
+};
+template <int HB>
+struct BitsetLds {
+  uint32_t As[kBitsetTile * kStageWords] __attribute__((aligned(16)));
+  uint32_t Bs[kBitsetTile * kStageWords] __attribute__((aligned(16)));
+  uint32_t hist[HB];
   uint32_t maxbin;
   int slot;
 };
 
-template <int WM>
+template <int WM, bool FP4>
 __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __restrict__ S,
                                                             int64_t n, int64_t ld,
                                                             unsigned long long* __restrict__ hist,
                                                             unsigned int* __restrict__ counter) {
-  constexpr int BM = 2 * WM * 32;
-  __shared__ TileLds<BM> L;
+  constexpr int BM = 2 * WM * 32, HB = kBinsSingle;
+  __shared__ MfmaLds<BM, HB> L;  // 96 KiB ring + 32 KiB bins at WM = 4
   const int64_t T = ceil_div(n, BM);
   const int64_t ntiles = T * (T + 1) / 2;
-  for (int b = threadIdx.x; b < kLdsBins; b += kThreads) L.hist[b] = 0;
+  for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
   uint32_t tmax = 0;
   int64_t pairs_in_lds = 0;
   TileArgs ta{(const uint32_t*)S, 2 * ld, n, 0, 0, hist};
@@ -405,25 +609,25 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
     int64_t I, J;
     tile_of(t, T, &I, &J);
     if (pairs_in_lds > (1ll << 31) - (int64_t)BM * BM) {  // keep uint32 LDS bins exact
-      flush_hist(L.hist, hist, n - 1, tmax, &L.maxbin);
+      flush_hist<HB>(L.hist, hist, n - 1, tmax, &L.maxbin);
       pairs_in_lds = 0;
     }
     ta.I0 = I * BM;
     ta.J0 = J * BM;
-    if (mfma_tile<WM>(ta, L.As, L.Bs, L.hist, tmax)) pairs_in_lds += (int64_t)BM * BM;
+    if (mfma_tile<WM, HB, FP4>(ta, L.ring, L.hist, tmax)) pairs_in_lds += (int64_t)BM * BM;
   }
-  flush_hist(L.hist, hist, n - 1, tmax, &L.maxbin);
+  flush_hist<HB>(L.hist, hist, n - 1, tmax, &L.maxbin);
 }
 
 __global__ __launch_bounds__(kThreads, 2) void k_count_bitset(const uint64_t* __restrict__ S,
                                                               int64_t n, int64_t ld,
                                                               unsigned long long* __restrict__ hist,
                                                               unsigned int* __restrict__ counter) {
-  constexpr int BM = kBitsetTile;
-  __shared__ TileLds<BM> L;
+  constexpr int BM = kBitsetTile, HB = kBinsSingle;
+  __shared__ BitsetLds<HB> L;
   const int64_t T = ceil_div(n, BM);
   const int64_t ntiles = T * (T + 1) / 2;
-  for (int b = threadIdx.x; b < kLdsBins; b += kThreads) L.hist[b] = 0;
+  for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
   uint32_t tmax = 0;
   int64_t pairs_in_lds = 0;
   TileArgs ta{(const uint32_t*)S, 2 * ld, n, 0, 0, hist};
@@ -433,32 +637,40 @@ __global__ __launch_bounds__(kThreads, 2) void k_count_bitset(const uint64_t* __
     int64_t I, J;
     tile_of(t, T, &I, &J);
     if (pairs_in_lds > (1ll << 31) - (int64_t)BM * BM) {
-      flush_hist(L.hist, hist, n - 1, tmax, &L.maxbin);
+      flush_hist<HB>(L.hist, hist, n - 1, tmax, &L.maxbin);
       pairs_in_lds = 0;
     }
     ta.I0 = I * BM;
     ta.J0 = J * BM;
-    if (bitset_tile(ta, L.As, L.Bs, L.hist, tmax)) pairs_in_lds += (int64_t)BM * BM;
+    if (bitset_tile<HB>(ta, L.As, L.Bs, L.hist, tmax)) pairs_in_lds += (int64_t)BM * BM;
   }
-  flush_hist(L.hist, hist, n - 1, tmax, &L.maxbin);
+  flush_hist<HB>(L.hist, hist, n - 1, tmax, &L.maxbin);
 }
 
 // ===========================================================================
-// Ensemble kernels: persistent over packed work items (instance << 16 | I << 8 | J),
-// ordered longest first across all instances.  The LDS histogram belongs to one
+// Ensemble kernels: persistent over packed row-panel items (instance << 16 | I << 8):
+// one item is every tile (I, J >= I) of one instance's row panel I, longest first.
+// Items are ordered by cost across all instances.  The LDS histogram belongs to one
 // instance at a time and is flushed when the workgroup moves to another instance.
 // Instance sizes are at most 8192, so every bin fits in LDS.
 // ===========================================================================
 template <int MODE>  // 0: bitset (128 tiles), 2 / 4: MFMA with WM = MODE
-__global__ __launch_bounds__(kThreads, 1) void k_count_batch(const uint64_t* __restrict__ bits,
-                                                             const BatchInst* __restrict__ inst,
-                                                             const uint32_t* __restrict__ items,
-                                                             int64_t nitems,
-                                                             unsigned long long* __restrict__ hist,
-                                                             unsigned int* __restrict__ counter) {
-  constexpr int BM = MODE == 0 ? kBitsetTile : 2 * MODE * 32;
-  __shared__ TileLds<BM> L;
-  for (int b = threadIdx.x; b < kLdsBins; b += kThreads) L.hist[b] = 0;
+struct BatchLdsOf {
+  using type = MfmaLds<2 * MODE * 32, kBinsBatch>;
+};
+template <>
+struct BatchLdsOf<0> {
+  using type = BitsetLds<kBinsBatch>;
+};
+
+template <int MODE, bool FP4 = false>
+__global__ __launch_bounds__(kThreads, MODE == 4 ? 1 : 2) void k_count_batch(
+    const uint64_t* __restrict__ bits, const BatchInst* __restrict__ inst,
+    const uint32_t* __restrict__ items, int64_t nitems, unsigned long long* __restrict__ hist,
+    unsigned int* __restrict__ counter) {
+  constexpr int BM = MODE == 0 ? kBitsetTile : 2 * MODE * 32, HB = kBinsBatch;
+  __shared__ typename BatchLdsOf<MODE>::type L;
+  for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
   uint32_t tmax = 0;
   int cur = -1;
   TileArgs ta{nullptr, 0, 0, 0, 0, nullptr};
@@ -468,7 +680,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_batch(const uint64_t* __r
     const uint32_t it = items[t];
     const int k = (int)(it >> 16);
     if (k != cur) {
-      if (cur >= 0) flush_hist(L.hist, ta.hist, ta.n - 1, tmax, &L.maxbin);
+      if (cur >= 0) flush_hist<HB>(L.hist, ta.hist, ta.n - 1, tmax, &L.maxbin);
       cur = k;
       const BatchInst d = inst[k];
       ta.S32 = (const uint32_t*)(bits + d.bits_off);
@@ -476,14 +688,18 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_batch(const uint64_t* __r
       ta.n = d.n;
       ta.hist = hist + d.hist_off;
     }
-    ta.I0 = (int64_t)((it >> 8) & 255u) * BM;
-    ta.J0 = (int64_t)(it & 255u) * BM;
-    if (MODE == 0)
-      bitset_tile(ta, L.As, L.Bs, L.hist, tmax);
-    else
-      mfma_tile<(MODE == 0 ? 2 : MODE)>(ta, L.As, L.Bs, L.hist, tmax);
+    const int64_t I = (int64_t)((it >> 8) & 255u);
+    const int64_t T = ceil_div(ta.n, BM);
+    ta.I0 = I * BM;
+    for (int64_t J = T - 1; J >= I; --J) {
+      ta.J0 = J * BM;
+      if constexpr (MODE == 0)
+        bitset_tile<HB>(ta, L.As, L.Bs, L.hist, tmax);
+      else
+        mfma_tile<MODE, HB, FP4>(ta, L.ring, L.hist, tmax);
+    }
   }
-  if (cur >= 0) flush_hist(L.hist, ta.hist, ta.n - 1, tmax, &L.maxbin);
+  if (cur >= 0) flush_hist<HB>(L.hist, ta.hist, ta.n - 1, tmax, &L.maxbin);
 }
 
 __global__ void k_fill_u64(uint64_t* __restrict__ p, int64_t count, uint64_t value) {
@@ -515,6 +731,18 @@ cs_status launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream_
 
 size_t histogram_ws_bytes(int64_t, int) { return 256; }
 
+template <int WM, bool FP4>
+cs_status launch_mfma(const uint64_t* bits, int64_t n, int64_t ld, uint64_t* hist,
+                      unsigned int* ctr, hipStream_t st) {
+  constexpr int BM = 2 * WM * 32;
+  const int64_t T = ceil_div(n, BM);
+  const unsigned grid = (unsigned)std::min<int64_t>(T * (T + 1) / 2, device_cu_count());
+  hipLaunchKernelGGL((k_count_mfma<WM, FP4>), dim3(grid), dim3(kThreads), 0, st, bits, n, ld,
+                     (unsigned long long*)hist, ctr);
+  CS_LAUNCH_CHECK();
+  return CS_OK;
+}
+
 cs_status launch_histogram(const uint64_t* bits, int64_t n, int64_t ld, int counter, uint64_t* hist,
                            void* ws, hipStream_t st) {
   unsigned int* ctr = (unsigned int*)ws;
@@ -522,52 +750,43 @@ cs_status launch_histogram(const uint64_t* bits, int64_t n, int64_t ld, int coun
   if (s != CS_OK) return s;
   s = launch_fill_u64((uint64_t*)ws, 1, 0, st);
   if (s != CS_OK) return s;
-  const int cus = device_cu_count();
-  if (counter == CS_COUNT_MFMA) {
-    if (n <= 4096) {
+  const bool big = n > 4096;  // 256x256 output tiles above 4096 points, 128x128 below
+  switch (counter) {
+    case CS_COUNT_MFMA:
+      return big ? launch_mfma<4, false>(bits, n, ld, hist, ctr, st)
+                 : launch_mfma<2, false>(bits, n, ld, hist, ctr, st);
+    case CS_COUNT_MFMA_FP4:
+      return big ? launch_mfma<4, true>(bits, n, ld, hist, ctr, st)
+                 : launch_mfma<2, true>(bits, n, ld, hist, ctr, st);
+    default: {
       const int64_t T = ceil_div(n, 128);
-      unsigned grid = (unsigned)std::min<int64_t>(T * (T + 1) / 2, cus);
-      hipLaunchKernelGGL(k_count_mfma<2>, dim3(grid), dim3(kThreads), 0, st, bits, n, ld,
+      const unsigned grid = (unsigned)std::min<int64_t>(T * (T + 1) / 2, 2 * device_cu_count());
+      hipLaunchKernelGGL(k_count_bitset, dim3(grid), dim3(kThreads), 0, st, bits, n, ld,
                          (unsigned long long*)hist, ctr);
-    } else {
-      const int64_t T = ceil_div(n, 256);
-      unsigned grid = (unsigned)std::min<int64_t>(T * (T + 1) / 2, cus);
-      hipLaunchKernelGGL(k_count_mfma<4>, dim3(grid), dim3(kThreads), 0, st, bits, n, ld,
-                         (unsigned long long*)hist, ctr);
+      CS_LAUNCH_CHECK();
+      return CS_OK;
     }
-  } else {
-    const int64_t T = ceil_div(n, 128);
-    unsigned grid = (unsigned)std::min<int64_t>(T * (T + 1) / 2, 2 * cus);
-    hipLaunchKernelGGL(k_count_bitset, dim3(grid), dim3(kThreads), 0, st, bits, n, ld,
-                       (unsigned long long*)hist, ctr);
   }
-  CS_LAUNCH_CHECK();
-  return CS_OK;
 }
 
-cs_status launch_count_batch(int mode, const uint64_t* bits, const BatchInst* inst,
+cs_status launch_count_batch(int mode, bool fp4, const uint64_t* bits, const BatchInst* inst,
                              const uint32_t* items, int64_t nitems, uint64_t* hist,
                              unsigned int* counter, hipStream_t st) {
   if (nitems <= 0) return CS_OK;
   const int cus = device_cu_count();
-  const int per_cu = mode == 4 ? 1 : 2;  // LDS: 80 KiB (256 tiles) or 72 KiB (128 tiles)
-  unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)cus * per_cu);
+  const int per_cu = mode == 4 ? 1 : 2;
+  const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)cus * per_cu);
   unsigned long long* h = (unsigned long long*)hist;
-  switch (mode) {
-    case 0:
-      hipLaunchKernelGGL(k_count_batch<0>, dim3(grid), dim3(kThreads), 0, st, bits, inst, items,
-                         nitems, h, counter);
-      break;
-    case 2:
-      hipLaunchKernelGGL(k_count_batch<2>, dim3(grid), dim3(kThreads), 0, st, bits, inst, items,
-                         nitems, h, counter);
-      break;
-    case 4:
-      hipLaunchKernelGGL(k_count_batch<4>, dim3(grid), dim3(kThreads), 0, st, bits, inst, items,
-                         nitems, h, counter);
-      break;
-    default: return CS_ERR_UNSUPPORTED;
-  }
+#define CS_BATCH_LAUNCH(M, F)                                                                  \
+  hipLaunchKernelGGL((k_count_batch<M, F>), dim3(grid), dim3(kThreads), 0, st, bits, inst, \
+                     items, nitems, h, counter)
+  if (mode == 0) CS_BATCH_LAUNCH(0, false);
+  else if (mode == 2 && !fp4) CS_BATCH_LAUNCH(2, false);
+  else if (mode == 4 && !fp4) CS_BATCH_LAUNCH(4, false);
+  else if (mode == 2 && fp4) CS_BATCH_LAUNCH(2, true);
+  else if (mode == 4 && fp4) CS_BATCH_LAUNCH(4, true);
+  else return CS_ERR_UNSUPPORTED;
+#undef CS_BATCH_LAUNCH
   CS_LAUNCH_CHECK();
   return CS_OK;
 }

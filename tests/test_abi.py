@@ -46,6 +46,7 @@ def test_sizes_and_strings(L):
     assert L.cs_sprinkle_workspace_bytes(1, 1000) > 0
     assert L.cs_sprinkle_workspace_bytes(7, 1000) == 0
     assert L.cs_histogram_workspace_bytes(1000, 1) > 0
+    assert L.cs_histogram_workspace_bytes(1000, 2) > 0
     assert L.cs_histogram_workspace_bytes(1000, 5) == 0
 
 
@@ -67,3 +68,26 @@ def test_argument_errors_need_no_device(L):
     assert L.cs_sprinkle(2, 2.0, 1, 100, p, p, 1 << 20, null) == 1
     assert L.cs_sprinkle(1, 0.0, 1, 1000, p, p, 16, null) == 3
     assert L.cs_interval_histogram(p, 100, 8, 1, p, p, 0, null) == 3
+    assert L.cs_interval_histogram(p, 1 << 24, 1 << 18, 2, p, p, 256, null) == 4  # fp4: n < 2^24
+
+
+def test_batch_plan_argument_errors_need_no_device(L):
+    import numpy as np
+    h = ctypes.c_void_p()
+    eps = np.array([0.0, 0.1])
+    ok = np.array([100, 200], dtype=np.int64)
+    big = np.array([100, 9000], dtype=np.int64)
+    tiny = np.array([1], dtype=np.int64)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert L.cs_batch_plan(2, P(big), 1, 2, P(eps), None, ctypes.byref(h)) == 1   # n > 8192
+    assert L.cs_batch_plan(1, P(tiny), 1, 2, P(eps), None, ctypes.byref(h)) == 1  # n < 2
+    assert L.cs_batch_plan(0, P(ok), 1, 2, P(eps), None, ctypes.byref(h)) == 1    # count
+    assert L.cs_batch_plan(2, P(ok), 7, 2, P(eps), None, ctypes.byref(h)) == 2    # counter
+    bad_eps = np.array([1.5])
+    assert L.cs_batch_plan(2, P(ok), 1, 1, P(bad_eps), None, ctypes.byref(h)) == 1
+    assert L.cs_batch_plan(2, P(ok), 1, 1, P(eps), None, None) == 1
+    assert L.cs_batch_run(None, None, None, None, None, 0, None) == 1
+    assert L.cs_batch_free(None) == 0
+    assert L.cs_batch_graph_launch(None, None) == 1
+    assert L.cs_batch_graph_destroy(None) == 0
+    assert L.cs_autotune(None, None) == 1

@@ -49,20 +49,21 @@ def check_instances(orc, plan, hist, acts, sizes, seeds, which):
             assert abs(got - want) <= 1e-12 * abs(want), (k, n, eps, got, want)
 
 
-@pytest.mark.parametrize("counter", [0, 1], ids=["bitset", "mfma"])
+@pytest.mark.parametrize("counter", [0, 1, 2], ids=["bitset", "mfma", "mfma_fp4"])
 def test_batch_mixed_sizes(cs, orc, counter):
     seeds = [1000 + 17 * k for k in range(len(SIZES))]
     plan, hist, acts = run_batch(cs, SIZES, seeds, counter)
     check_instances(orc, plan, hist, acts, SIZES, seeds, range(len(SIZES)))
 
 
+@pytest.mark.parametrize("counter", [1, 2], ids=["mfma", "mfma_fp4"])
 @pytest.mark.parametrize("thr", [2, 100000], ids=["all256", "all128"])
-def test_batch_tile_shapes(cs, orc, tmp_path, thr):
+def test_batch_tile_shapes(cs, orc, tmp_path, thr, counter):
     cache = tmp_path / "tune.json"
     cache.write_text(json.dumps({"tile256_min_n": thr}))
     sizes = [130, 700, 2500, 4100, 8000]
     seeds = [77, 78, 79, 80, 81]
-    plan, hist, acts = run_batch(cs, sizes, seeds, 1, tune_cache=str(cache))
+    plan, hist, acts = run_batch(cs, sizes, seeds, counter, tune_cache=str(cache))
     check_instances(orc, plan, hist, acts, sizes, seeds, range(len(sizes)))
 
 

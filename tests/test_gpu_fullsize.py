@@ -62,7 +62,7 @@ def test_mink4_n16384_whole_path(cs, orc):
     assert np.array_equal(c.cpu().numpy(), coords)
     b = cs.cs_causal_matrix(W.MINK4_DIAMOND, c)
     assert np.array_equal(host_u64(b), bits)
-    for counter in (cs.CS_COUNT_MFMA, cs.CS_COUNT_BITSET):
+    for counter in (cs.CS_COUNT_MFMA, cs.CS_COUNT_BITSET, cs.CS_COUNT_MFMA_FP4):
         h = cs.cs_interval_histogram(b, n, counter)
         assert np.array_equal(host_u64(h), hist)
         for eps, want in acts.items():
@@ -81,7 +81,8 @@ def test_ds4_n65536(cs, orc):
     del want
     hm = host_u64(cs.cs_interval_histogram(b, n, cs.CS_COUNT_MFMA)).copy()
     hb = host_u64(cs.cs_interval_histogram(b, n, cs.CS_COUNT_BITSET)).copy()
-    assert np.array_equal(hm, hb)
+    hf = host_u64(cs.cs_interval_histogram(b, n, cs.CS_COUNT_MFMA_FP4)).copy()
+    assert np.array_equal(hm, hb) and np.array_equal(hm, hf)
     assert int(hm.sum()) == rel
     assert int((np.arange(n - 1, dtype=np.uint64) * hm).sum()) == chains3
     # the GPU sprinkle from the same seed agrees to a few ulps
@@ -104,7 +105,8 @@ def test_mink4_n131072(cs, orc):
     del got
     hm = host_u64(cs.cs_interval_histogram(b, n, cs.CS_COUNT_MFMA)).copy()
     hb = host_u64(cs.cs_interval_histogram(b, n, cs.CS_COUNT_BITSET)).copy()
-    assert np.array_equal(hm, hb)
+    hf = host_u64(cs.cs_interval_histogram(b, n, cs.CS_COUNT_MFMA_FP4)).copy()
+    assert np.array_equal(hm, hb) and np.array_equal(hm, hf)
     assert int(hm.sum()) == rel
     assert int((np.arange(n - 1, dtype=np.uint64) * hm).sum()) == c3
     # ordering fraction of the 3+1 diamond is 1/10 (sd of R/(N(N-1)/2) at this N is ~1e-3)

@@ -123,3 +123,12 @@ def test_matrix_against_vectorised_predicate(orc, region):
         dot = ((c[3][i] * c[3][j] + c[4][i] * c[4][j]) + c[5][i] * c[5][j]) + c[6][i] * c[6][j]
         r = (c[0][i] < c[0][j]) & (cd < dot)
     assert np.array_equal(S[i, j], r)
+
+
+@pytest.mark.parametrize("region", [W.MINK2_DIAMOND, W.MINK4_DIAMOND, W.DS4_SLAB])
+def test_sampled_rows_equal_full_matrix(orc, region):
+    n = 1100
+    c = orc.sprinkle(region, n, seed=61)
+    full = orc.causal_matrix(region, c)
+    rows = [0, 1, 63, 64, 65, 500, 1098, 1099]
+    assert np.array_equal(orc.causal_rows(region, c, rows), full[rows])

@@ -187,6 +187,14 @@ cs_status cs_batch_graph_destroy(void *graph_exec);
  */
 cs_status cs_autotune(const char *cache_path, void *stream);
 
+/*
+ * Measurement utility (not part of the pipeline): the int8 (counter = CS_COUNT_MFMA) or fp4
+ * (CS_COUNT_MFMA_FP4) MFMA throughput this device sustains, in TOP/s, from a register-only
+ * MFMA stream on every CU (best of two timed launches after a warm-up).  Allocates and frees
+ * a few KiB of device memory and synchronises `stream`.  *tops is host memory.
+ */
+cs_status cs_measure_mfma_peak(int counter, double *tops, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,7 @@ SYMBOLS = [
     "cs_sprinkle", "cs_causal_matrix", "cs_histogram_workspace_bytes", "cs_interval_histogram",
     "cs_action", "cs_batch_plan", "cs_batch_workspace_bytes", "cs_batch_hist_len",
     "cs_batch_hist_offset", "cs_batch_run", "cs_batch_free", "cs_batch_graph_create",
-    "cs_batch_graph_launch", "cs_batch_graph_destroy", "cs_autotune",
+    "cs_batch_graph_launch", "cs_batch_graph_destroy", "cs_autotune", "cs_measure_mfma_peak",
 ]
 
 
@@ -65,6 +65,7 @@ def lib():
             "cs_batch_graph_launch": (c_int, [p, p]),
             "cs_batch_graph_destroy": (c_int, [p]),
             "cs_autotune": (c_int, [ctypes.c_char_p, p]),
+            "cs_measure_mfma_peak": (c_int, [c_int, ctypes.POINTER(dbl), p]),
         }
         for name, (res, args) in sig.items():
             if hasattr(L, name):
@@ -221,3 +222,11 @@ class BatchGraph:
 
 def cs_autotune(cache_path: str, stream=None):
     _check(lib().cs_autotune(cache_path.encode(), _stream(stream)), "cs_autotune")
+
+
+def cs_measure_mfma_peak(counter: int, stream=None) -> float:
+    """Sustained MFMA throughput (TOP/s) of the operand type of `counter` on this device."""
+    out = ctypes.c_double(0.0)
+    _check(lib().cs_measure_mfma_peak(counter, ctypes.byref(out), _stream(stream)),
+           "cs_measure_mfma_peak")
+    return out.value

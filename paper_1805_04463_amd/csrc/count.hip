@@ -234,12 +234,27 @@ __device__ inline void dma_stage(__amdgpu_buffer_rsrc_t rsrc, uint32_t lds_stage
     const int32_t vo = voff_row[q] < 0 ? (int32_t)0x80000000 : voff_row[q] + kbyte;
     const uint32_t lds_addr = lds_stage_addr + wave_off + q * kThreads * 16;
     // Issued as inline assembly so the compiler does not add its own wait for the DMA
-    // before every LDS read; completion is tracked explicitly with wait_vmcnt.
-    asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
-                 :
-                 : "s"(lds_addr), "v"(vo), "s"(rsrc)
-                 : "memory", "m0");
+    // before every LDS read; completion is tracked explicitly with wait_vmcnt.  M0 (the
+    // DMA's LDS address) is saved and restored around the load.
+    uint32_t m0_save;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\tbuffer_load_dwordx4 %2, %3, 0 offen lds\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(m0_save)
+        : "s"(lds_addr), "v"(vo), "s"(rsrc)
+        : "memory");
   }
+}
+
+// Buffer descriptor of a panel (base, byte range), its fields made wave-uniform so they
+// live in scalar registers whatever the compiler can prove about their origin.
+__device__ inline __amdgpu_buffer_rsrc_t uniform_rsrc(const uint32_t* base, uint32_t bytes) {
+  const uint64_t p = (uint64_t)(uintptr_t)base;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+  const uint32_t nr = __builtin_amdgcn_readfirstlane(bytes);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)(((uint64_t)hi << 32) | lo), (short)0,
+                                           (int)nr, 0x00020000);
 }
 
 // Panel byte offsets (row part + chunk) of this thread's DMA slots; -1 marks rows >= n.
@@ -386,7 +401,7 @@ __device__ inline void mfma_stage(
 }
 
 template <int WM, int HB, bool FP4 = false>
-__device__ inline bool mfma_tile(const TileArgs& ta, uint32_t* ring, uint32_t* lds_hist,
+__device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& ta, uint32_t* ring, uint32_t* lds_hist,
                                  uint32_t& tmax) {
   using Acc = typename std::conditional<FP4, v16f, v16i>::type;
   constexpr int BM = 2 * WM * 32;
@@ -413,10 +428,10 @@ __device__ inline bool mfma_tile(const TileArgs& ta, uint32_t* ring, uint32_t* l
   const int64_t kend = (J0 + BM < n ? J0 + BM : n);
   const int nst = (int)ceil_div(kend - kbeg, kMStageBits);
   const int64_t va = n - I0 < BM ? n - I0 : BM, vb = n - J0 < BM ? n - J0 : BM;
-  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(ta.S32 + I0 * ta.ld32), (short)0, (int)(va * ld * 8), 0x00020000);
-  const __amdgpu_buffer_rsrc_t rbf = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(ta.S32 + J0 * ta.ld32), (short)0, (int)(vb * ld * 8), 0x00020000);
+  const __amdgpu_buffer_rsrc_t ra =
+      uniform_rsrc(ta.S32 + I0 * ta.ld32, (uint32_t)(va * ld * 8));
+  const __amdgpu_buffer_rsrc_t rbf =
+      uniform_rsrc(ta.S32 + J0 * ta.ld32, (uint32_t)(vb * ld * 8));
   int32_t oa[kPer], ob[kPer];
   dma_offsets<BM>(oa, ld, va);
   dma_offsets<BM>(ob, ld, vb);
@@ -572,6 +587,82 @@ __device__ inline bool bitset_tile(const TileArgs& ta, uint32_t* As, uint32_t* B
 }
 
 // ===========================================================================
+// XCD-aware tile schedule for the MFMA counters.
+//
+// The MI355X's 256 CUs sit in 8 XCDs, each with its own L2.  Tiles that share a row
+// panel of S (same I) or a column panel (same J) can share its fetches from HBM when
+// they run at the same time on the same XCD.  So output tiles are grouped into
+// rectangles of 4 x 8 tiles (I in [4a, 4a+4), J in [8b, 8b+8)): 32 tiles, one per CU of
+// an XCD, reading 4 + 8 panels instead of 64.  Rectangles are ordered by their
+// distance from the diagonal (k = 2b - a, cost ~ J - I), longest first, and dealt
+// round-robin to 8 queues; a workgroup serves the queue of the XCD it runs on
+// (hardware register XCC_ID) and then takes work from the other queues, so all tiles
+// are done whatever the mapping of workgroups to XCDs.
+// ===========================================================================
+constexpr int kRA = 4, kRB = 8, kRect = kRA * kRB, kQueues = 8;
+constexpr int kMaxK = 2048;  // entries of the per-k rectangle table (T <= 8184)
+
+struct RectSched {
+  int64_t T, NA, NB, R;     // tiles per side, rectangle grid, rectangles touching j >= i
+  int K, kmax;              // k = kmax - index, index in [0, K)
+  int pre[kMaxK + 1];       // rectangles with larger k (exclusive prefix)
+  int lo[kMaxK];            // first b of the k-diagonal
+};
+
+__device__ inline bool rect_sched_fits(int64_t T) { return 2 * ceil_div(T, kRB) + 2 <= kMaxK; }
+
+// Fills the table (one workgroup, called by every workgroup at kernel start).
+__device__ inline void rect_sched_init(RectSched& rs, int64_t T) {
+  if (threadIdx.x == 0) {
+    rs.T = T;
+    rs.NA = ceil_div(T, kRA);
+    rs.NB = ceil_div(T, kRB);
+    rs.kmax = (int)(2 * (rs.NB - 1));
+    rs.K = rs.kmax + 2;  // k from kmax down to -1 (k >= -1 <=> rectangle reaches j >= i)
+    int acc = 0;
+    for (int t = 0; t < rs.K; ++t) {
+      const int64_t k = rs.kmax - t;
+      // b with a = 2b - k in [0, NA): b in [ceil(k/2), floor((NA-1+k)/2)], and b in [0, NB)
+      int64_t lo = k > 0 ? (k + 1) / 2 : 0;
+      int64_t hi = (rs.NA - 1 + k) >= 0 ? (rs.NA - 1 + k) / 2 : -1;
+      if (hi > rs.NB - 1) hi = rs.NB - 1;
+      rs.lo[t] = (int)lo;
+      rs.pre[t] = acc;
+      acc += hi >= lo ? (int)(hi - lo + 1) : 0;
+    }
+    rs.pre[rs.K] = acc;
+    rs.R = acc;
+  }
+  __syncthreads();
+}
+
+// Item q of queue x -> tile (I, J); false if the slot is past the queue or no tile.
+__device__ inline bool rect_tile(const RectSched& rs, int x, int64_t q, int64_t* I, int64_t* J) {
+  const int64_t r = (q / kRect) * kQueues + x;
+  if (r >= rs.R) return false;
+  int lo = 0, hi = rs.K - 1;  // last t with pre[t] <= r
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rs.pre[mid] <= r) lo = mid; else hi = mid - 1;
+  }
+  const int64_t k = rs.kmax - lo;
+  const int64_t b = rs.lo[lo] + (r - rs.pre[lo]);
+  const int64_t a = 2 * b - k;
+  const int p = (int)(q % kRect);
+  *I = kRA * a + p / kRB;
+  *J = kRB * b + p % kRB;
+  return *I <= *J && *J < rs.T;
+}
+
+__device__ inline int64_t rect_queue_len(const RectSched& rs, int x) {
+  return rs.R > x ? ((rs.R - x + kQueues - 1) / kQueues) * kRect : 0;
+}
+
+__device__ inline int xcc_id() {
+  return (int)__builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11)) & (kQueues - 1);
+}
+
+// ===========================================================================
 // Single-instance kernels: persistent over the T(T+1)/2 tiles, longest first.
 // ===========================================================================
 template <int BM, int HB>
@@ -580,6 +671,10 @@ struct MfmaLds {
   uint32_t hist[HB];
   uint32_t maxbin;
   int slot;
+};
+template <int BM, int HB>
+struct MfmaLdsSched : MfmaLds<BM, HB> {
+  RectSched rs;
 };
 template <int HB>
 struct BitsetLds {
@@ -596,18 +691,35 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
                                                             unsigned long long* __restrict__ hist,
                                                             unsigned int* __restrict__ counter) {
   constexpr int BM = 2 * WM * 32, HB = kBinsSingle;
-  __shared__ MfmaLds<BM, HB> L;  // 96 KiB ring + 32 KiB bins at WM = 4
+  __shared__ MfmaLdsSched<BM, HB> L;  // 96 KiB ring + 32 KiB bins + 16 KiB table at WM = 4
   const int64_t T = ceil_div(n, BM);
-  const int64_t ntiles = T * (T + 1) / 2;
   for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
   uint32_t tmax = 0;
   int64_t pairs_in_lds = 0;
   TileArgs ta{(const uint32_t*)S, 2 * ld, n, 0, 0, hist};
+  // Rectangle queues per XCD while the table fits; beyond that (very large n) one queue,
+  // longest K-range first.
+  const bool rect = rect_sched_fits(T);
+  if (rect) rect_sched_init(L.rs, T);
+  const int x0 = xcc_id();
+  const int64_t ntiles = T * (T + 1) / 2;
+  int probe = 0;
   for (;;) {
-    const int64_t t = next_tile(counter, &L.slot);
-    if (t >= ntiles) break;
     int64_t I, J;
-    tile_of(t, T, &I, &J);
+    if (rect) {
+      if (probe >= kQueues) break;
+      const int x = (x0 + probe) & (kQueues - 1);
+      const int64_t q = next_tile(counter + x, &L.slot);
+      if (q >= rect_queue_len(L.rs, x)) {
+        ++probe;
+        continue;
+      }
+      if (!rect_tile(L.rs, x, q, &I, &J)) continue;
+    } else {
+      const int64_t t = next_tile(counter, &L.slot);
+      if (t >= ntiles) break;
+      tile_of(t, T, &I, &J);
+    }
     if (pairs_in_lds > (1ll << 31) - (int64_t)BM * BM) {  // keep uint32 LDS bins exact
       flush_hist<HB>(L.hist, hist, n - 1, tmax, &L.maxbin);
       pairs_in_lds = 0;
@@ -748,7 +860,7 @@ cs_status launch_histogram(const uint64_t* bits, int64_t n, int64_t ld, int coun
   unsigned int* ctr = (unsigned int*)ws;
   cs_status s = launch_fill_u64(hist, n - 1, 0, st);
   if (s != CS_OK) return s;
-  s = launch_fill_u64((uint64_t*)ws, 1, 0, st);
+  s = launch_fill_u64((uint64_t*)ws, 4, 0, st);  // 8 queue counters
   if (s != CS_OK) return s;
   const bool big = n > 4096;  // 256x256 output tiles above 4096 points, 128x128 below
   switch (counter) {

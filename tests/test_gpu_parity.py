@@ -156,3 +156,10 @@ def test_pipeline_mink2_n1024(cs, orc, counter):
     for eps, want in acts.items():
         got = cs.cs_action(h, n, 2, eps).item()
         assert abs(got - want) <= 1e-12 * abs(want)
+
+
+def test_measured_mfma_peaks_are_plausible(cs):
+    int8 = cs.cs_measure_mfma_peak(cs.CS_COUNT_MFMA)
+    fp4 = cs.cs_measure_mfma_peak(cs.CS_COUNT_MFMA_FP4)
+    assert 1000 < int8 < 5100      # TOP/s; published dense int8 peak 5000
+    assert 2000 < fp4 < 10300      # published dense fp4 peak 10100

@@ -34,6 +34,7 @@
 //          costs two VALU ops per four bytes.
 //   BITSET AND + v_bcnt_u32_b32 on 32-bit words, each thread an 8x8 block of pairs.
 #include <type_traits>
+#include <utility>
 
 #include "common.h"
 
@@ -279,31 +280,26 @@ __device__ inline uint32_t word_of(const uint4& v, int w) {
   return w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w;
 }
 
-// Bits S[j][i] for rows i in [rb + 32 mb, +32) of column j = J0 + 32 (WM wc + nb) + l32,
-// restricted to i < j (so only related pairs of the upper triangle remain).
-template <int WM>
-__device__ inline uint32_t related_word(const TileArgs& ta, int64_t rb, int mb, int wc, int nb,
-                                        int l32) {
-  const int64_t j = ta.J0 + wc * (WM * 32) + nb * 32 + l32;
-  if (j >= ta.n) return 0u;
-  const int64_t i0 = rb + mb * 32;
-  return ta.S32[j * ta.ld32 + (i0 >> 5)] & mask_below(i0, j);
-}
-
-// The same 128 bits of K on the fp4 matrix cores (v_mfma_scale_f32_32x32x64_f8f6f4 with
-// both operands in e2m1, unit scales).  Each MFMA takes 64 k: lanes 0-31 take word 2u of
-// the chunk, lanes 32-63 word 2u+1.  Bit k becomes the e2m1 code 0b0010 (= 1.0) or 0
-// in nibble m of register q for k = q + 4m (a permutation of k shared by A and B), two
-// VALU ops per register.  Products are 0 or 1 and every count is below 2^24, so the
-// f32 accumulation is exact.
+// fp4 matrix cores (v_mfma_scale_f32_32x32x64_f8f6f4, both operands e2m1).  A lane's
+// 128-bit chunk (words q = 0..3) feeds four MFMAs, one per bit class c: register q of
+// class c holds bits c, c+4, ..., c+28 of word q, each left in its own nibble, so no
+// bit moves except for class 3.  Bit positions 0, 1, 2 of a nibble are the e2m1 codes
+// 0.5, 1.0 and 2.0; the per-block E8M0 scales 2, 1, 1/2 (codes 128, 127, 126) bring
+// every operand to 0 or 1, and class 3 is shifted down to position 0.  Products are
+// 0 or 1 and every count is below 2^24, so the f32 accumulation is exact.
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-__device__ inline v8i unpack_fp4(uint32_t x) {
-  const uint32_t x2 = x << 1;
-  return (v8i){(int)(x2 & 0x22222222u), (int)((x >> 0) & 0x22222222u),
-               (int)((x >> 1) & 0x22222222u), (int)((x >> 2) & 0x22222222u), 0, 0, 0, 0};
+template <int C>
+__device__ inline v8i unpack_fp4_class(const uint4& v) {
+  if constexpr (C == 3)
+    return (v8i){(int)((v.x >> 3) & 0x11111111u), (int)((v.y >> 3) & 0x11111111u),
+                 (int)((v.z >> 3) & 0x11111111u), (int)((v.w >> 3) & 0x11111111u), 0, 0, 0, 0};
+  constexpr uint32_t m = 0x11111111u << C;
+  return (v8i){(int)(v.x & m), (int)(v.y & m), (int)(v.z & m), (int)(v.w & m), 0, 0, 0, 0};
 }
+template <int C>
+constexpr int fp4_class_scale() { return C == 1 ? 127 : C == 2 ? 126 : 128; }
 
 // Triangular masks on a chunk: keep k > row for A words, k < row for B words.  da / db are
 // the offsets of the chunk's first bit from the lane's first A row / B row.
@@ -327,67 +323,92 @@ __device__ inline void mask_chunk(uint4 (&aw)[WM], uint4 (&bw)[WM], int32_t da, 
   }
 }
 
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time.
+template <typename F, int... I>
+__device__ inline void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ inline void static_for(F&& f) {
+  static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
 // One stage (512 bits of K = 4 chunks of 128) as a flat, software-pipelined sequence of
-// k-steps: the operands of step t+1 are unpacked while the MFMAs of step t issue, and
-// the scheduler is told to interleave them (one MFMA, then a share of the VALU work), so
-// the matrix pipe is fed without bubbles and only two sets of operands are live.  The
-// LDS words of chunk c+1 are read while chunk c is multiplied.
+// k-steps.  Lanes 0-31 take chunks 0 and 1 of every row, lanes 32-63 chunks 2 and 3:
+// the MFMA's K order only has to be the same for A and B, and with this assignment
+// each half-wave reads just the chunks it multiplies.  A chunk gives 4 fp4 k-steps
+// (one per bit class) or 8 int8 k-steps (word w, nibble e of every byte: bits
+// 32w + 4e + q + 8b in byte b of register q).  The operands of step t+1 are unpacked
+// while the MFMAs of step t issue, and the scheduler is told to interleave them (one
+// MFMA, then a share of the VALU work).  Chunk 1 is read while chunk 0 is multiplied.
 template <int WM, bool FP4>
 __device__ inline void mfma_stage(
     typename std::conditional<FP4, v16f, v16i>::type (&acc)[WM][WM], const uint32_t* As,
-    const uint32_t* Bs, int arow, int brow, bool masked, int32_t da, int32_t db, uint32_t sh,
-    int hsel) {
-  constexpr int kSteps = FP4 ? 2 : 4;     // MFMA k-steps per 128-bit chunk
-  constexpr int kT = 4 * kSteps;          // k-steps per stage
+    const uint32_t* Bs, int arow, int brow, bool masked, int32_t da, int32_t db, int hsel) {
+  constexpr int kSteps = FP4 ? 4 : 8;     // MFMA k-steps per 128-bit chunk
+  constexpr int kT = 2 * kSteps;          // k-steps per stage
   using Frag = typename std::conditional<FP4, v8i, v4i>::type;
+  const int c0 = 2 * hsel;                // this half-wave's first chunk
   uint4 aw[2][WM], bw[2][WM];
   Frag af[2][WM], bf[2][WM];
-  auto load_chunk = [&](int c, uint4 (&a)[WM], uint4 (&b)[WM]) {
+  auto load_chunk = [&](int cc, uint4 (&a)[WM], uint4 (&b)[WM]) {
 #pragma unroll
-    for (int mb = 0; mb < WM; ++mb) a[mb] = *(const uint4*)(As + mpos(arow + mb * 32, c));
+    for (int mb = 0; mb < WM; ++mb) a[mb] = *(const uint4*)(As + mpos(arow + mb * 32, c0 + cc));
 #pragma unroll
-    for (int nb = 0; nb < WM; ++nb) b[nb] = *(const uint4*)(Bs + mpos(brow + nb * 32, c));
+    for (int nb = 0; nb < WM; ++nb) b[nb] = *(const uint4*)(Bs + mpos(brow + nb * 32, c0 + cc));
   };
-  auto unpack_step = [&](const uint4 (&a)[WM], const uint4 (&b)[WM], int w, Frag (&fa)[WM],
-                         Frag (&fb)[WM]) {
+  auto mask = [&](int cc) {
+    mask_chunk<WM>(aw[cc], bw[cc], da + (c0 + cc) * 128, db + (c0 + cc) * 128);
+  };
+  auto unpack_step = [&](auto step, int cc, Frag (&fa)[WM], Frag (&fb)[WM]) {
+    constexpr int u = decltype(step)::value;  // step within the chunk
 #pragma unroll
     for (int mb = 0; mb < WM; ++mb) {
-      if constexpr (FP4) fa[mb] = unpack_fp4(word_of(a[mb], 2 * w + hsel));
-      else fa[mb] = unpack_i8(word_of(a[mb], w), sh);
+      if constexpr (FP4) fa[mb] = unpack_fp4_class<u>(aw[cc][mb]);
+      else fa[mb] = unpack_i8(word_of(aw[cc][mb], u >> 1), 4u * (u & 1));
     }
 #pragma unroll
     for (int nb = 0; nb < WM; ++nb) {
-      if constexpr (FP4) fb[nb] = unpack_fp4(word_of(b[nb], 2 * w + hsel));
-      else fb[nb] = unpack_i8(word_of(b[nb], w), sh);
+      if constexpr (FP4) fb[nb] = unpack_fp4_class<u>(bw[cc][nb]);
+      else fb[nb] = unpack_i8(word_of(bw[cc][nb], u >> 1), 4u * (u & 1));
     }
   };
-  load_chunk(0, aw[0], bw[0]);
-  if (masked) mask_chunk<WM>(aw[0], bw[0], da, db);
-  unpack_step(aw[0], bw[0], 0, af[0], bf[0]);
-#pragma unroll
-  for (int t = 0; t < kT; ++t) {
-    const int c = t / kSteps, w = t % kSteps, cur = t & 1;
-    if (w == 0 && c + 1 < 4) load_chunk(c + 1, aw[(c + 1) & 1], bw[(c + 1) & 1]);
-    if (t + 1 < kT) {
-      const int cn = (t + 1) / kSteps, wn = (t + 1) % kSteps;
-      if (wn == 0 && masked) mask_chunk<WM>(aw[cn & 1], bw[cn & 1], da + cn * 128, db + cn * 128);
-      unpack_step(aw[cn & 1], bw[cn & 1], wn, af[cur ^ 1], bf[cur ^ 1]);
-    }
+  auto mfmas = [&](auto step, const Frag (&fa)[WM], const Frag (&fb)[WM]) {
+    constexpr int u = decltype(step)::value;
 #pragma unroll
     for (int mb = 0; mb < WM; ++mb)
 #pragma unroll
       for (int nb = 0; nb < WM; ++nb) {
-        if constexpr (FP4)
+        if constexpr (FP4) {
+          constexpr int sc = fp4_class_scale<u>();
           acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-              af[cur][mb], bf[cur][nb], acc[mb][nb], 4, 4, 0, 127, 0, 127);
-        else
-          acc[mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[cur][mb], bf[cur][nb],
-                                                             acc[mb][nb], 0, 0, 0);
+              fa[mb], fb[nb], acc[mb][nb], 4, 4, 0, sc, 0, sc);
+        } else {
+          acc[mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[mb], fb[nb], acc[mb][nb], 0, 0, 0);
+        }
       }
-    if (t + 1 < kT) {
-      // 2 WM unpacked registers of 4 (int8) per MFMA row/column: spread the next step's
-      // VALU work evenly between this step's WM*WM MFMAs.
-      constexpr int kValu = (FP4 ? 7 : 8) * 2 * WM / (WM * WM) + 1;
+  };
+  load_chunk(0, aw[0], bw[0]);
+  if (masked) mask(0);
+  unpack_step(std::integral_constant<int, 0>{}, 0, af[0], bf[0]);
+  static_for<kT>([&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    constexpr int cur = t & 1;
+    if constexpr (t == 0) load_chunk(1, aw[1], bw[1]);
+    if constexpr (t + 1 < kT) {
+      constexpr int cn = (t + 1) / kSteps, un = (t + 1) % kSteps;
+      if constexpr (un == 0) {
+        if (masked) mask(cn);
+      }
+      unpack_step(std::integral_constant<int, un>{}, cn, af[cur ^ 1], bf[cur ^ 1]);
+    }
+    mfmas(std::integral_constant<int, t % kSteps>{}, af[cur], bf[cur]);
+    if constexpr (t + 1 < kT) {
+      // The next step's unpacking (2 WM fragments of 4 registers, 1 or 2 VALU ops each)
+      // spread evenly between this step's WM*WM MFMAs.
+      constexpr int un = (t + 1) % kSteps;
+      constexpr int kOps = FP4 ? (un == 3 ? 2 : 1) : 2;
+      constexpr int kValu = kOps * 4 * 2 * WM / (WM * WM) + 1;
 #pragma unroll
       for (int q = 0; q < WM * WM; ++q) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);      // one MFMA
@@ -397,12 +418,13 @@ __device__ inline void mfma_stage(
     // Keep each step's MFMAs in their own scheduling region: MFMAs of consecutive steps
     // update the same accumulators and must not be placed back to back.
     __builtin_amdgcn_sched_barrier(0);
-  }
+  });
 }
 
 template <int WM, int HB, bool FP4 = false>
-__device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& ta, uint32_t* ring, uint32_t* lds_hist,
-                                 uint32_t& tmax) {
+__device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& ta, uint32_t* ring,
+                                                                uint32_t* rel, uint32_t* lds_hist,
+                                                                uint32_t& tmax) {
   using Acc = typename std::conditional<FP4, v16f, v16i>::type;
   constexpr int BM = 2 * WM * 32;
   constexpr int kStage = BM * kMStageU32;      // one panel stage, uint32 words
@@ -413,15 +435,6 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   const int hsel = lane >> 5, l32 = lane & 31;
   const int64_t n = ta.n, I0 = ta.I0, J0 = ta.J0, nbins = n - 1;
   const int64_t rb = I0 + wr * (WM * 32);  // first output row of this wave
-
-  // Skip the tile if none of its pairs is related.  The bit words are loaded again in
-  // the epilogue rather than kept live through the K loop.
-  bool any = false;
-#pragma unroll
-  for (int nb = 0; nb < WM; ++nb)
-#pragma unroll
-    for (int mb = 0; mb < WM; ++mb) any |= related_word<WM>(ta, rb, mb, wc, nb, l32) != 0;
-  if (!__syncthreads_or(any)) return false;
 
   const int64_t ld = ta.ld32 >> 1;
   const int64_t kbeg = I0;
@@ -437,14 +450,6 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   dma_offsets<BM>(ob, ld, vb);
   const int32_t kbyte0 = (int32_t)(kbeg >> 3);
 
-  Acc acc[WM][WM];
-#pragma unroll
-  for (int a = 0; a < WM; ++a)
-#pragma unroll
-    for (int b = 0; b < WM; ++b)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[a][b][e] = 0;
-
   // LDS byte address of the ring (the low 32 bits of a generic LDS pointer).
   const uint32_t ring_addr = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)ring);
   constexpr int kMRing = MRing<BM>::value;
@@ -456,7 +461,37 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
       dma_stage<BM>(rbf, st + kStage * 4, ob, kbyte0 + p * (kMStageBits / 8));
     }
   }
-  const uint32_t sh = 4u * (uint32_t)hsel;
+  {
+    // The B panel's K range starts at I0, so its first stage holds S[j][i] for every
+    // pair of the tile: keep the bits with i < j (the related pairs the tile bins) in
+    // LDS for the epilogue, and skip the tile if there are none.
+    if (kMRing > 2 && nst > 1) wait_vmcnt<kLoads>();
+    else wait_vmcnt<0>();
+    __syncthreads();
+    bool any = false;
+    const uint32_t* Bs0 = ring + kStage;
+#pragma unroll
+    for (int nb = 0; nb < WM; ++nb)
+#pragma unroll
+      for (int mb = 0; mb < WM; ++mb) {
+        const int br = wc * (WM * 32) + nb * 32 + l32, m = wr * WM + mb;
+        const uint32_t w = Bs0[mpos(br, m >> 2) + (m & 3)] & mask_below(I0 + 32 * m, J0 + br);
+        any |= w != 0u;
+        if (hsel == 0) rel[((wave * WM + nb) * WM + mb) * 32 + l32] = w;
+      }
+    if (!__syncthreads_or(any)) {
+      wait_vmcnt<0>();  // drain the DMA of later stages before the ring is reused
+      return false;
+    }
+  }
+  Acc acc[WM][WM];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WM; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[a][b][e] = 0;
+
   const int arow = wr * WM * 32 + l32, brow = wc * WM * 32 + l32;
   const int32_t da0 = (int32_t)(kbeg - rb - l32);
   const int32_t db0 = (int32_t)(kbeg - J0 - wc * (WM * 32) - l32);
@@ -475,7 +510,7 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
     const int64_t kb = kbeg + (int64_t)s * kMStageBits;
     const bool masked = kb < I0 + BM || kb + kMStageBits > J0;  // touches a diagonal block
     const int32_t dst = da0 + s * kMStageBits, dbs = db0 + s * kMStageBits;
-    mfma_stage<WM, FP4>(acc, As, Bs, arow, brow, masked, dst, dbs, sh, hsel);
+    mfma_stage<WM, FP4>(acc, As, Bs, arow, brow, masked, dst, dbs, hsel);
   }
 
   // Epilogue.  32x32 accumulator layout: lane holds column (lane & 31) and rows
@@ -484,7 +519,7 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   for (int nb = 0; nb < WM; ++nb) {
 #pragma unroll
     for (int mb = 0; mb < WM; ++mb) {
-      const uint32_t w = related_word<WM>(ta, rb, mb, wc, nb, l32);
+      const uint32_t w = rel[((wave * WM + nb) * WM + mb) * 32 + l32];
       if (!w) continue;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
@@ -668,6 +703,7 @@ __device__ inline int xcc_id() {
 template <int BM, int HB>
 struct MfmaLds {
   uint32_t ring[MRing<BM>::value * 2 * BM * kMStageU32] __attribute__((aligned(16)));
+  uint32_t rel[BM * BM / 32];  // relation bits of the current tile's pairs (i < j)
   uint32_t hist[HB];
   uint32_t maxbin;
   int slot;
@@ -726,7 +762,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
     }
     ta.I0 = I * BM;
     ta.J0 = J * BM;
-    if (mfma_tile<WM, HB, FP4>(ta, L.ring, L.hist, tmax)) pairs_in_lds += (int64_t)BM * BM;
+    if (mfma_tile<WM, HB, FP4>(ta, L.ring, L.rel, L.hist, tmax)) pairs_in_lds += (int64_t)BM * BM;
   }
   flush_hist<HB>(L.hist, hist, n - 1, tmax, &L.maxbin);
 }
@@ -808,7 +844,7 @@ __global__ __launch_bounds__(kThreads, MODE == 4 ? 1 : 2) void k_count_batch(
       if constexpr (MODE == 0)
         bitset_tile<HB>(ta, L.As, L.Bs, L.hist, tmax);
       else
-        mfma_tile<MODE, HB, FP4>(ta, L.ring, L.hist, tmax);
+        mfma_tile<MODE, HB, FP4>(ta, L.ring, L.rel, L.hist, tmax);
     }
   }
   if (cur >= 0) flush_hist<HB>(L.hist, ta.hist, ta.n - 1, tmax, &L.maxbin);

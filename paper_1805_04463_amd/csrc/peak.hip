@@ -57,7 +57,7 @@ using namespace cs;
 extern "C" cs_status cs_measure_mfma_peak(int counter, double* tops, void* stream) {
   if (!tops || (counter != CS_COUNT_MFMA && counter != CS_COUNT_MFMA_FP4)) return CS_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
-  const int blocks = device_cu_count(), iters = 2000;
+  const int blocks = device_cu_count(), iters = 20000;  // ~5 ms per launch
   int *din = nullptr, *dout = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   cs_status s = CS_OK;

@@ -118,6 +118,9 @@ size_t cs_histogram_workspace_bytes(int64_t n, int counter);
  *   counter  CS_COUNT_BITSET, CS_COUNT_MFMA or CS_COUNT_MFMA_FP4; identical results.
  *   hist     device, n-1 uint64, overwritten (zeroed by the callee).
  *   workspace device, at least cs_histogram_workspace_bytes(n, counter) bytes.
+ * The MFMA counters address a 256-row panel of the matrix with 32-bit offsets and
+ * need ld_words <= 2^19 (a panel below 1 GiB, n up to 33.5 million); larger strides
+ * give CS_ERR_OVERFLOW.  CS_COUNT_MFMA_FP4 also needs n < 2^24.
  */
 cs_status cs_interval_histogram(const uint64_t *bits, int64_t n, int64_t ld_words, int counter,
                                 uint64_t *hist, void *workspace, size_t workspace_bytes,

@@ -9,6 +9,9 @@ using namespace cs;
 namespace {
 
 constexpr int64_t kMaxN = (int64_t)1 << 31;
+// MFMA counters: a 256-row panel (256 * ld_words * 8 bytes) stays below 1 GiB, so panel
+// offsets fit the buffer descriptors' 32-bit range with room for out-of-range requests.
+constexpr int64_t kMaxMfmaLd = (int64_t)1 << 19;
 
 inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
@@ -79,6 +82,7 @@ cs_status cs_interval_histogram(const uint64_t* bits, int64_t n, int64_t ld_word
   if (s != CS_OK) return s;
   if (!bits || !hist || !workspace || ld_words_ < ld_words(n)) return CS_ERR_INVALID_ARG;
   if (counter == CS_COUNT_MFMA_FP4 && n >= (int64_t)1 << 24) return CS_ERR_OVERFLOW;
+  if (counter != CS_COUNT_BITSET && ld_words_ > kMaxMfmaLd) return CS_ERR_OVERFLOW;
   if (workspace_bytes < histogram_ws_bytes(n, counter)) return CS_ERR_WORKSPACE;
   return launch_histogram(bits, n, ld_words_, counter, hist, workspace, as_stream(stream));
 }

@@ -211,6 +211,9 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 // request covers half a 128-byte line and a line is consumed by two neighbouring
 // stages.  Within a stage, row r's four 16-byte chunks sit at positions c ^ (r/4 mod 4)
 // so that sixteen consecutive rows reading the same chunk hit distinct banks.
+#ifndef CS_DMA_STEPS
+#define CS_DMA_STEPS(steps) ((steps) / 2)
+#endif
 constexpr int kMStageBits = 512;
 constexpr int kMStageU32 = kMStageBits / 32;  // uint32 words per row per stage
 // Stages in the LDS ring: three for 256-row panels (one workgroup per CU), two for
@@ -222,29 +225,34 @@ struct MRing {
 
 __device__ inline int mpos(int r, int c) { return r * kMStageU32 + ((c ^ ((r >> 2) & 3)) << 2); }
 
-// One stage of a BM-row panel into an LDS stage buffer by DMA: thread t issues
-// BM*4/256 loads of 16 bytes; issue q of wave w writes slots q*256 + 64w + lane,
-// slot s = 4r + (c ^ (r/4 mod 4)).
+// One 16-byte-per-lane DMA request of a stage: load q (of BM*4/256) of a BM-row panel
+// into an LDS stage buffer; request q of wave w writes slots q*256 + 64w + lane, slot
+// s = 4r + (c ^ (r/4 mod 4)).
+template <int BM>
+__device__ inline void dma_one(__amdgpu_buffer_rsrc_t rsrc, uint32_t lds_stage_addr, int32_t voff,
+                               int32_t kbyte, int q) {
+  const uint32_t wave_off = __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) * 64 * 16);
+  const int32_t vo = voff < 0 ? (int32_t)0x80000000 : voff + kbyte;
+  const uint32_t lds_addr = lds_stage_addr + wave_off + q * kThreads * 16;
+  // Issued as inline assembly so the compiler does not add its own wait for the DMA
+  // before every LDS read; completion is tracked explicitly with wait_vmcnt.  M0 (the
+  // DMA's LDS address) is saved and restored around the load.
+  uint32_t m0_save;
+  asm volatile(
+      "s_mov_b32 %[sv], m0\n\ts_mov_b32 m0, %[la]\n\t"
+      "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\ts_mov_b32 m0, %[sv]"
+      : [sv] "=&s"(m0_save)
+      : [la] "s"(lds_addr), [vo] "v"(vo), [rs] "s"(rsrc)
+      : "memory");
+}
+
+// A whole stage of a BM-row panel (BM*4/256 requests per thread).
 template <int BM>
 __device__ inline void dma_stage(__amdgpu_buffer_rsrc_t rsrc, uint32_t lds_stage_addr,
                                  const int32_t* voff_row, int32_t kbyte) {
   constexpr int kPer = BM * 4 / kThreads;
-  const uint32_t wave_off = __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) * 64 * 16);
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int32_t vo = voff_row[q] < 0 ? (int32_t)0x80000000 : voff_row[q] + kbyte;
-    const uint32_t lds_addr = lds_stage_addr + wave_off + q * kThreads * 16;
-    // Issued as inline assembly so the compiler does not add its own wait for the DMA
-    // before every LDS read; completion is tracked explicitly with wait_vmcnt.  M0 (the
-    // DMA's LDS address) is saved and restored around the load.
-    uint32_t m0_save;
-    asm volatile(
-        "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\tbuffer_load_dwordx4 %2, %3, 0 offen lds\n\t"
-        "s_mov_b32 m0, %0"
-        : "=&s"(m0_save)
-        : "s"(lds_addr), "v"(vo), "s"(rsrc)
-        : "memory");
-  }
+  for (int q = 0; q < kPer; ++q) dma_one<BM>(rsrc, lds_stage_addr, voff_row[q], kbyte, q);
 }
 
 // Buffer descriptor of a panel (base, byte range), its fields made wave-uniform so they
@@ -301,25 +309,29 @@ __device__ inline v8i unpack_fp4_class(const uint4& v) {
 template <int C>
 constexpr int fp4_class_scale() { return C == 1 ? 127 : C == 2 ? 126 : 128; }
 
-// Triangular masks on a chunk: keep k > row for A words, k < row for B words.  da / db are
-// the offsets of the chunk's first bit from the lane's first A row / B row.
-template <int WM>
-__device__ inline void mask_chunk(uint4 (&aw)[WM], uint4 (&bw)[WM], int32_t da, int32_t db) {
+// Triangular masks applied in place to a stage in LDS, on the stages that overlap a
+// diagonal block of the tile: A rows (i = I0 + r) keep k > i, B rows (j = J0 + r) keep
+// k < j, for the stage's bits k in [kb, kb + 512).  The masks depend only on the row and
+// k, so one pass serves every wave that reads the row.
+template <int BM>
+__device__ inline void mask_stage(uint32_t* As, uint32_t* Bs, int64_t kb, int64_t I0, int64_t J0) {
+  for (int x = threadIdx.x; x < 2 * BM; x += kThreads) {
+    const bool is_a = x < BM;
+    const int r = is_a ? x : x - BM;
+    uint32_t* P = is_a ? As : Bs;
+    const int64_t g = (is_a ? I0 : J0) + r;
 #pragma unroll
-  for (int mb = 0; mb < WM; ++mb) {
-    const int32_t d = da - mb * 32;
-    aw[mb].x &= mask_above_d(d);
-    aw[mb].y &= mask_above_d(d + 32);
-    aw[mb].z &= mask_above_d(d + 64);
-    aw[mb].w &= mask_above_d(d + 96);
-  }
+    for (int c = 0; c < 4; ++c) {
+      uint4 v = *(uint4*)(P + mpos(r, c));
+      uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-  for (int nb = 0; nb < WM; ++nb) {
-    const int32_t d = db - nb * 32;
-    bw[nb].x &= mask_below_d(d);
-    bw[nb].y &= mask_below_d(d + 32);
-    bw[nb].z &= mask_below_d(d + 64);
-    bw[nb].w &= mask_below_d(d + 96);
+      for (int q = 0; q < 4; ++q) {
+        int64_t d = kb + 128 * c + 32 * q - g;  // word start minus the row index
+        d = d < -64 ? -64 : (d > 64 ? 64 : d);
+        w[q] &= is_a ? mask_above_d((int32_t)d) : mask_below_d((int32_t)d);
+      }
+      *(uint4*)(P + mpos(r, c)) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
   }
 }
 
@@ -341,12 +353,15 @@ __device__ inline void static_for(F&& f) {
 // 32w + 4e + q + 8b in byte b of register q).  The operands of step t+1 are unpacked
 // while the MFMAs of step t issue, and the scheduler is told to interleave them (one
 // MFMA, then a share of the VALU work).  Chunk 1 is read while chunk 0 is multiplied.
-template <int WM, bool FP4>
+template <int WM, bool FP4, int kLoads, typename Dma>
 __device__ inline void mfma_stage(
     typename std::conditional<FP4, v16f, v16i>::type (&acc)[WM][WM], const uint32_t* As,
-    const uint32_t* Bs, int arow, int brow, bool masked, int32_t da, int32_t db, int hsel) {
+    const uint32_t* Bs, int arow, int brow, int hsel, Dma&& dma) {
   constexpr int kSteps = FP4 ? 4 : 8;     // MFMA k-steps per 128-bit chunk
   constexpr int kT = 2 * kSteps;          // k-steps per stage
+  // The kLoads DMA requests for a later stage are spread over the first kDmaSteps steps.
+  constexpr int kDmaSteps = CS_DMA_STEPS(kT);
+  constexpr int kPerStep = (kLoads + kDmaSteps - 1) / kDmaSteps;
   using Frag = typename std::conditional<FP4, v8i, v4i>::type;
   const int c0 = 2 * hsel;                // this half-wave's first chunk
   uint4 aw[2][WM], bw[2][WM];
@@ -356,9 +371,6 @@ __device__ inline void mfma_stage(
     for (int mb = 0; mb < WM; ++mb) a[mb] = *(const uint4*)(As + mpos(arow + mb * 32, c0 + cc));
 #pragma unroll
     for (int nb = 0; nb < WM; ++nb) b[nb] = *(const uint4*)(Bs + mpos(brow + nb * 32, c0 + cc));
-  };
-  auto mask = [&](int cc) {
-    mask_chunk<WM>(aw[cc], bw[cc], da + (c0 + cc) * 128, db + (c0 + cc) * 128);
   };
   auto unpack_step = [&](auto step, int cc, Frag (&fa)[WM], Frag (&fb)[WM]) {
     constexpr int u = decltype(step)::value;  // step within the chunk
@@ -389,7 +401,6 @@ __device__ inline void mfma_stage(
       }
   };
   load_chunk(0, aw[0], bw[0]);
-  if (masked) mask(0);
   unpack_step(std::integral_constant<int, 0>{}, 0, af[0], bf[0]);
   static_for<kT>([&](auto tc) {
     constexpr int t = decltype(tc)::value;
@@ -397,10 +408,16 @@ __device__ inline void mfma_stage(
     if constexpr (t == 0) load_chunk(1, aw[1], bw[1]);
     if constexpr (t + 1 < kT) {
       constexpr int cn = (t + 1) / kSteps, un = (t + 1) % kSteps;
-      if constexpr (un == 0) {
-        if (masked) mask(cn);
-      }
       unpack_step(std::integral_constant<int, un>{}, cn, af[cur ^ 1], bf[cur ^ 1]);
+    }
+    static_assert(kDmaSteps < kT, "DMA pieces go between steps");
+    if constexpr (t < kDmaSteps) {
+      // This step's share of the DMA (the stage is one basic block, so the per-step
+      // scheduling barrier keeps it within the step).
+      static_for<kPerStep>([&](auto qc) {
+        constexpr int q = t * kPerStep + decltype(qc)::value;
+        if constexpr (q < kLoads) dma(std::integral_constant<int, q>{});
+      });
     }
     mfmas(std::integral_constant<int, t % kSteps>{}, af[cur], bf[cur]);
     if constexpr (t + 1 < kT) {
@@ -434,7 +451,6 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   const int wr = wave >> 1, wc = wave & 1;
   const int hsel = lane >> 5, l32 = lane & 31;
   const int64_t n = ta.n, I0 = ta.I0, J0 = ta.J0, nbins = n - 1;
-  const int64_t rb = I0 + wr * (WM * 32);  // first output row of this wave
 
   const int64_t ld = ta.ld32 >> 1;
   const int64_t kbeg = I0;
@@ -465,8 +481,10 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
     // The B panel's K range starts at I0, so its first stage holds S[j][i] for every
     // pair of the tile: keep the bits with i < j (the related pairs the tile bins) in
     // LDS for the epilogue, and skip the tile if there are none.
-    if (kMRing > 2 && nst > 1) wait_vmcnt<kLoads>();
-    else wait_vmcnt<0>();
+    // Wait for everything, stage 1 included (it was issued right after stage 0): this also
+    // retires the previous tile's global histogram atomics, so the compiler has no
+    // outstanding memory operation to wait for inside the stage loop.
+    wait_vmcnt<0>();
     __syncthreads();
     bool any = false;
     const uint32_t* Bs0 = ring + kStage;
@@ -493,25 +511,33 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
       for (int e = 0; e < 16; ++e) acc[a][b][e] = 0;
 
   const int arow = wr * WM * 32 + l32, brow = wc * WM * 32 + l32;
-  const int32_t da0 = (int32_t)(kbeg - rb - l32);
-  const int32_t db0 = (int32_t)(kbeg - J0 - wc * (WM * 32) - l32);
   for (int s = 0; s < nst; ++s) {
     if (kMRing > 2 && s + 1 < nst) wait_vmcnt<kLoads>();  // stage s+1 may stay in flight
     else wait_vmcnt<0>();
     __syncthreads();  // stage s visible to all waves; all waves are done with stage s-1
-    if (s + kMRing - 1 < nst) {
-      const uint32_t st = ring_addr + ((s + kMRing - 1) % kMRing) * 2 * kStage * 4;
-      const int32_t kb = kbyte0 + (s + kMRing - 1) * (kMStageBits / 8);
-      dma_stage<BM>(ra, st, oa, kb);
-      dma_stage<BM>(rbf, st + kStage * 4, ob, kb);
-    }
-    const uint32_t* As = ring + (s % kMRing) * 2 * kStage;
-    const uint32_t* Bs = As + kStage;
+    uint32_t* As = ring + (s % kMRing) * 2 * kStage;
+    uint32_t* Bs = As + kStage;
     const int64_t kb = kbeg + (int64_t)s * kMStageBits;
-    const bool masked = kb < I0 + BM || kb + kMStageBits > J0;  // touches a diagonal block
-    const int32_t dst = da0 + s * kMStageBits, dbs = db0 + s * kMStageBits;
-    mfma_stage<WM, FP4>(acc, As, Bs, arow, brow, masked, dst, dbs, hsel);
+    if (kb < I0 + BM || kb + kMStageBits > J0) {  // the stage overlaps a diagonal block
+      mask_stage<BM>(As, Bs, kb, I0, J0);
+      __syncthreads();
+    }
+    // DMA of stage s + kMRing - 1 into the slot every wave finished reading in stage s-1,
+    // issued in pieces between this stage's MFMAs.  Past the last stage the requests are
+    // pushed out of the descriptors' range (panels are far below 1 GiB), so they read
+    // nothing; issuing them anyway keeps the code free of branches that would let the
+    // compiler gather all requests in one place.
+    const uint32_t dst_slot = ring_addr + ((s + kMRing - 1) % kMRing) * 2 * kStage * 4;
+    const int32_t dkb = s + kMRing - 1 < nst ? kbyte0 + (s + kMRing - 1) * (kMStageBits / 8)
+                                             : (int32_t)0x40000000;
+    auto dma = [&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      if constexpr (q < kPer) dma_one<BM>(ra, dst_slot, oa[q], dkb, q);
+      else dma_one<BM>(rbf, dst_slot + kStage * 4, ob[q - kPer], dkb, q - kPer);
+    };
+    mfma_stage<WM, FP4, kLoads>(acc, As, Bs, arow, brow, hsel, dma);
   }
+  wait_vmcnt<0>();  // the out-of-range requests of the last stages, before the ring is reused
 
   // Epilogue.  32x32 accumulator layout: lane holds column (lane & 31) and rows
   // 8*(e/4) + 4*(lane/32) + (e%4) for e = 0..15.

@@ -69,6 +69,9 @@ def test_argument_errors_need_no_device(L):
     assert L.cs_sprinkle(1, 0.0, 1, 1000, p, p, 16, null) == 3
     assert L.cs_interval_histogram(p, 100, 8, 1, p, p, 0, null) == 3
     assert L.cs_interval_histogram(p, 1 << 24, 1 << 18, 2, p, p, 256, null) == 4  # fp4: n < 2^24
+    # MFMA counters: 256-row panels must stay below 1 GiB (ld_words <= 2^19)
+    assert L.cs_interval_histogram(p, 1000, (1 << 19) + 1, 1, p, p, 256, null) == 4
+    assert L.cs_interval_histogram(p, 1000, (1 << 19) + 1, 2, p, p, 256, null) == 4
 
 
 def test_batch_plan_argument_errors_need_no_device(L):

@@ -540,17 +540,39 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   wait_vmcnt<0>();  // the out-of-range requests of the last stages, before the ring is reused
 
   // Epilogue.  32x32 accumulator layout: lane holds column (lane & 31) and rows
-  // 8*(e/4) + 4*(lane/32) + (e%4) for e = 0..15.
+  // 8*(e/4) + 4*(lane/32) + (e%4) for e = 0..15.  Branch-free binning: key = the pair's
+  // count if it is related, else 0xFFFFFFFF (unrelated pairs all have count 0).  Every
+  // element issues one LDS add, to its bin when key < HB and otherwise to this lane's own
+  // word past the bins, so misses neither touch a bin nor collide with other lanes.  The
+  // flush range is capped at HB, so tmax may take the spare word's index.  Counts of HB
+  // or more are rare: a second pass over the block, behind a wave-uniform test, adds
+  // them to the global histogram.
+  const uint32_t spare = (uint32_t)HB + (uint32_t)lane;
 #pragma unroll
   for (int nb = 0; nb < WM; ++nb) {
 #pragma unroll
     for (int mb = 0; mb < WM; ++mb) {
-      const uint32_t w = rel[((wave * WM + nb) * WM + mb) * 32 + l32];
-      if (!w) continue;
+      const uint32_t w = rel[((wave * WM + nb) * WM + mb) * 32 + l32] >> (4 * hsel);
+      if (!__ballot(w != 0u)) continue;  // no related pair in this 32x32 block
+      const uint32_t wn = ~w;
+      uint32_t big = 0;  // max over the block of key + 1 (0 for unrelated pairs)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int il = (e >> 2) * 8 + hsel * 4 + (e & 3);
-        if ((w >> il) & 1u) bin_add<HB>(lds_hist, ta.hist, (uint32_t)acc[mb][nb][e], nbins, tmax);
+        const int sh = (e >> 2) * 8 + (e & 3);
+        const uint32_t key = (uint32_t)acc[mb][nb][e] | (uint32_t)(-(int32_t)((wn >> sh) & 1u));
+        const uint32_t slot = key < (uint32_t)HB ? key : spare;
+        atomicAdd(lds_hist + slot, 1u);
+        tmax = slot > tmax ? slot : tmax;
+        big = key + 1u > big ? key + 1u : big;
+      }
+      if (__ballot(big > (uint32_t)HB)) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int sh = (e >> 2) * 8 + (e & 3);
+          const uint32_t bin = (uint32_t)acc[mb][nb][e];
+          if (((w >> sh) & 1u) && bin >= (uint32_t)HB && (int64_t)bin < nbins)
+            atomicAdd(ta.hist + bin, 1ull);
+        }
       }
     }
   }
@@ -730,7 +752,7 @@ template <int BM, int HB>
 struct MfmaLds {
   uint32_t ring[MRing<BM>::value * 2 * BM * kMStageU32] __attribute__((aligned(16)));
   uint32_t rel[BM * BM / 32];  // relation bits of the current tile's pairs (i < j)
-  uint32_t hist[HB];
+  uint32_t hist[HB + 64];      // bins, then one spare word per lane (never flushed)
   uint32_t maxbin;
   int slot;
 };

@@ -352,25 +352,32 @@ __device__ inline void static_for(F&& f) {
 // (one per bit class) or 8 int8 k-steps (word w, nibble e of every byte: bits
 // 32w + 4e + q + 8b in byte b of register q).  The operands of step t+1 are unpacked
 // while the MFMAs of step t issue, and the scheduler is told to interleave them (one
-// MFMA, then a share of the VALU work).  Chunk 1 is read while chunk 0 is multiplied.
-template <int WM, bool FP4, int kLoads, typename Dma>
-__device__ inline void mfma_stage(
-    typename std::conditional<FP4, v16f, v16i>::type (&acc)[WM][WM], const uint32_t* As,
-    const uint32_t* Bs, int arow, int brow, int hsel, Dma&& dma) {
-  constexpr int kSteps = FP4 ? 4 : 8;     // MFMA k-steps per 128-bit chunk
-  constexpr int kT = 2 * kSteps;          // k-steps per stage
-  // The kLoads DMA requests for a later stage are spread over the first kDmaSteps steps.
-  constexpr int kDmaSteps = CS_DMA_STEPS(kT);
-  constexpr int kPerStep = (kLoads + kDmaSteps - 1) / kDmaSteps;
-  using Frag = typename std::conditional<FP4, v8i, v4i>::type;
-  const int c0 = 2 * hsel;                // this half-wave's first chunk
-  uint4 aw[2][WM], bw[2][WM];
-  Frag af[2][WM], bf[2][WM];
-  auto load_chunk = [&](int cc, uint4 (&a)[WM], uint4 (&b)[WM]) {
+// MFMA, then a share of the VALU work).
+//
+// Stages are chained without a gap.  On entry the registers hold this stage's chunk 0
+// (aw[0], bw[0]) and the operands of its first step (af[0], bf[0]).  Chunk 1 is read
+// at the first step.  After the first half every operand of the stage is in registers,
+// so `mid` (wait for the next stage's DMA, barrier) both publishes the next stage and
+// frees this stage's slot: the second half reads the next stage's chunk 0, issues the
+// DMA pieces (`dma`) that refill this slot, and unpacks the next stage's first step.
+// MODE 0: a plain stage follows; 1: the tile's last stage follows (`mid` masks it);
+// 2: this is the tile's last stage.
+template <int WM, bool FP4, int kLoads, int MODE, typename Acc, typename Frag, typename Mid,
+          typename Dma>
+__device__ inline void mfma_stage(Acc (&acc)[WM][WM], uint4 (&aw)[2][WM], uint4 (&bw)[2][WM],
+                                  Frag (&af)[2][WM], Frag (&bf)[2][WM], const uint32_t* As,
+                                  const uint32_t* Bs, const uint32_t* An, const uint32_t* Bn,
+                                  int arow, int brow, int hsel, Mid&& mid, Dma&& dma) {
+  constexpr int kSteps = FP4 ? 4 : 8;  // MFMA k-steps per 128-bit chunk
+  constexpr int kT = 2 * kSteps;       // k-steps per stage
+  constexpr int kPerStep = (kLoads + kSteps - 1) / kSteps;  // DMA pieces per step, 2nd half
+  const int c0 = 2 * hsel;             // this half-wave's first chunk
+  auto load_chunk = [&](const uint32_t* A, const uint32_t* B, int cc, uint4 (&a)[WM],
+                        uint4 (&b)[WM]) {
 #pragma unroll
-    for (int mb = 0; mb < WM; ++mb) a[mb] = *(const uint4*)(As + mpos(arow + mb * 32, c0 + cc));
+    for (int mb = 0; mb < WM; ++mb) a[mb] = *(const uint4*)(A + mpos(arow + mb * 32, c0 + cc));
 #pragma unroll
-    for (int nb = 0; nb < WM; ++nb) b[nb] = *(const uint4*)(Bs + mpos(brow + nb * 32, c0 + cc));
+    for (int nb = 0; nb < WM; ++nb) b[nb] = *(const uint4*)(B + mpos(brow + nb * 32, c0 + cc));
   };
   auto unpack_step = [&](auto step, int cc, Frag (&fa)[WM], Frag (&fb)[WM]) {
     constexpr int u = decltype(step)::value;  // step within the chunk
@@ -400,30 +407,26 @@ __device__ inline void mfma_stage(
         }
       }
   };
-  load_chunk(0, aw[0], bw[0]);
-  unpack_step(std::integral_constant<int, 0>{}, 0, af[0], bf[0]);
   static_for<kT>([&](auto tc) {
     constexpr int t = decltype(tc)::value;
     constexpr int cur = t & 1;
-    if constexpr (t == 0) load_chunk(1, aw[1], bw[1]);
-    if constexpr (t + 1 < kT) {
-      constexpr int cn = (t + 1) / kSteps, un = (t + 1) % kSteps;
-      unpack_step(std::integral_constant<int, un>{}, cn, af[cur ^ 1], bf[cur ^ 1]);
-    }
-    static_assert(kDmaSteps < kT, "DMA pieces go between steps");
-    if constexpr (t < kDmaSteps) {
+    if constexpr (t == 0) load_chunk(As, Bs, 1, aw[1], bw[1]);
+    if constexpr (t == kSteps && MODE != 2) load_chunk(An, Bn, 0, aw[0], bw[0]);
+    if constexpr (t >= kSteps) {
       // This step's share of the DMA (the stage is one basic block, so the per-step
       // scheduling barrier keeps it within the step).
       static_for<kPerStep>([&](auto qc) {
-        constexpr int q = t * kPerStep + decltype(qc)::value;
+        constexpr int q = (t - kSteps) * kPerStep + decltype(qc)::value;
         if constexpr (q < kLoads) dma(std::integral_constant<int, q>{});
       });
     }
+    constexpr bool unpack = t + 1 < kT || MODE != 2;
+    constexpr int un = (t + 1) % kSteps, cn = ((t + 1) / kSteps) & 1;  // next stage: chunk 0
+    if constexpr (unpack) unpack_step(std::integral_constant<int, un>{}, cn, af[cur ^ 1], bf[cur ^ 1]);
     mfmas(std::integral_constant<int, t % kSteps>{}, af[cur], bf[cur]);
-    if constexpr (t + 1 < kT) {
+    if constexpr (unpack) {
       // The next step's unpacking (2 WM fragments of 4 registers, 1 or 2 VALU ops each)
       // spread evenly between this step's WM*WM MFMAs.
-      constexpr int un = (t + 1) % kSteps;
       constexpr int kOps = FP4 ? (un == 3 ? 2 : 1) : 2;
       constexpr int kValu = kOps * 4 * 2 * WM / (WM * WM) + 1;
 #pragma unroll
@@ -435,6 +438,7 @@ __device__ inline void mfma_stage(
     // Keep each step's MFMAs in their own scheduling region: MFMAs of consecutive steps
     // update the same accumulators and must not be placed back to back.
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (t == kSteps - 1) mid();
   });
 }
 
@@ -468,23 +472,28 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
 
   // LDS byte address of the ring (the low 32 bits of a generic LDS pointer).
   const uint32_t ring_addr = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)ring);
-  constexpr int kMRing = MRing<BM>::value;
-#pragma unroll
-  for (int p = 0; p < kMRing - 1; ++p) {  // prologue: stages 0 .. kMRing-2 in flight
-    if (p < nst) {
-      const uint32_t st = ring_addr + p * 2 * kStage * 4;
-      dma_stage<BM>(ra, st, oa, kbyte0 + p * (kMStageBits / 8));
-      dma_stage<BM>(rbf, st + kStage * 4, ob, kbyte0 + p * (kMStageBits / 8));
-    }
-  }
+  constexpr int R = MRing<BM>::value;
+  // DMA of stage st into its ring slot; past the last stage the requests are pushed out
+  // of the descriptors' range (panels are below 1 GiB), so they read nothing.  Issuing
+  // them anyway keeps the stage code free of branches, which would let the compiler
+  // gather all requests in one place.
+  auto dma_piece = [&](int st, auto qc) {
+    constexpr int q = decltype(qc)::value;
+    const uint32_t slot = ring_addr + (st % R) * 2 * kStage * 4;
+    const int32_t kb = st < nst ? kbyte0 + st * (kMStageBits / 8) : (int32_t)0x40000000;
+    if constexpr (q < kPer) dma_one<BM>(ra, slot, oa[q], kb, q);
+    else dma_one<BM>(rbf, slot + kStage * 4, ob[q - kPer], kb, q - kPer);
+  };
+  // The previous tile's global histogram atomics: retiring them here leaves the compiler
+  // no outstanding memory operation to wait for inside the stage loop.
+  wait_vmcnt<0>();
+  for (int st = 0; st < R; ++st)  // prologue: stages 0 .. R-1
+    static_for<kLoads>([&](auto qc) { dma_piece(st, qc); });
   {
     // The B panel's K range starts at I0, so its first stage holds S[j][i] for every
     // pair of the tile: keep the bits with i < j (the related pairs the tile bins) in
     // LDS for the epilogue, and skip the tile if there are none.
-    // Wait for everything, stage 1 included (it was issued right after stage 0): this also
-    // retires the previous tile's global histogram atomics, so the compiler has no
-    // outstanding memory operation to wait for inside the stage loop.
-    wait_vmcnt<0>();
+    wait_vmcnt<(R - 1) * kLoads>();
     __syncthreads();
     bool any = false;
     const uint32_t* Bs0 = ring + kStage;
@@ -502,6 +511,31 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
       return false;
     }
   }
+  // Only the first and the last stage overlap a diagonal block (the A rows' block lies
+  // in stage 0, the B rows' block in the last stage); both are masked in LDS before they
+  // are read, the first here, the last halfway through the stage before it.
+  mask_stage<BM>(ring, ring + kStage, kbeg, I0, J0);
+  __syncthreads();
+
+  using Frag = typename std::conditional<FP4, v8i, v4i>::type;
+  const int arow = wr * WM * 32 + l32, brow = wc * WM * 32 + l32;
+  uint4 aw[2][WM], bw[2][WM];
+  Frag af[2][WM], bf[2][WM];
+#pragma unroll
+  for (int mb = 0; mb < WM; ++mb) aw[0][mb] = *(const uint4*)(ring + mpos(arow + mb * 32, 2 * hsel));
+#pragma unroll
+  for (int nb = 0; nb < WM; ++nb)
+    bw[0][nb] = *(const uint4*)(ring + kStage + mpos(brow + nb * 32, 2 * hsel));
+#pragma unroll
+  for (int mb = 0; mb < WM; ++mb) {
+    if constexpr (FP4) af[0][mb] = unpack_fp4_class<0>(aw[0][mb]);
+    else af[0][mb] = unpack_i8(aw[0][mb].x, 0u);
+  }
+#pragma unroll
+  for (int nb = 0; nb < WM; ++nb) {
+    if constexpr (FP4) bf[0][nb] = unpack_fp4_class<0>(bw[0][nb]);
+    else bf[0][nb] = unpack_i8(bw[0][nb].x, 0u);
+  }
   Acc acc[WM][WM];
 #pragma unroll
   for (int a = 0; a < WM; ++a)
@@ -510,33 +544,27 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[a][b][e] = 0;
 
-  const int arow = wr * WM * 32 + l32, brow = wc * WM * 32 + l32;
-  for (int s = 0; s < nst; ++s) {
-    if (kMRing > 2 && s + 1 < nst) wait_vmcnt<kLoads>();  // stage s+1 may stay in flight
-    else wait_vmcnt<0>();
-    __syncthreads();  // stage s visible to all waves; all waves are done with stage s-1
-    uint32_t* As = ring + (s % kMRing) * 2 * kStage;
-    uint32_t* Bs = As + kStage;
-    const int64_t kb = kbeg + (int64_t)s * kMStageBits;
-    if (kb < I0 + BM || kb + kMStageBits > J0) {  // the stage overlaps a diagonal block
-      mask_stage<BM>(As, Bs, kb, I0, J0);
+  auto stage = [&](auto modec, int s) {
+    constexpr int MODE = decltype(modec)::value;
+    const uint32_t* As = ring + (s % R) * 2 * kStage;
+    const uint32_t* An = ring + ((s + 1) % R) * 2 * kStage;
+    auto mid = [&]() {
+      if constexpr (MODE != 2) wait_vmcnt<(R - 2) * kLoads>();  // stage s+1 has landed
       __syncthreads();
-    }
-    // DMA of stage s + kMRing - 1 into the slot every wave finished reading in stage s-1,
-    // issued in pieces between this stage's MFMAs.  Past the last stage the requests are
-    // pushed out of the descriptors' range (panels are far below 1 GiB), so they read
-    // nothing; issuing them anyway keeps the code free of branches that would let the
-    // compiler gather all requests in one place.
-    const uint32_t dst_slot = ring_addr + ((s + kMRing - 1) % kMRing) * 2 * kStage * 4;
-    const int32_t dkb = s + kMRing - 1 < nst ? kbyte0 + (s + kMRing - 1) * (kMStageBits / 8)
-                                             : (int32_t)0x40000000;
-    auto dma = [&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      if constexpr (q < kPer) dma_one<BM>(ra, dst_slot, oa[q], dkb, q);
-      else dma_one<BM>(rbf, dst_slot + kStage * 4, ob[q - kPer], dkb, q - kPer);
+      if constexpr (MODE == 1) {
+        mask_stage<BM>(ring + ((s + 1) % R) * 2 * kStage, ring + ((s + 1) % R) * 2 * kStage + kStage,
+                       kbeg + (int64_t)(s + 1) * kMStageBits, I0, J0);
+        __syncthreads();
+      }
     };
-    mfma_stage<WM, FP4, kLoads>(acc, As, Bs, arow, brow, hsel, dma);
-  }
+    auto dma = [&](auto qc) { dma_piece(s + R, qc); };  // refills this stage's slot
+    mfma_stage<WM, FP4, kLoads, MODE>(acc, aw, bw, af, bf, As, As + kStage, An, An + kStage, arow,
+                                      brow, hsel, mid, dma);
+  };
+  int s = 0;
+  for (; s + 2 < nst; ++s) stage(std::integral_constant<int, 0>{}, s);
+  if (nst >= 2) stage(std::integral_constant<int, 1>{}, s++);
+  stage(std::integral_constant<int, 2>{}, s);
   wait_vmcnt<0>();  // the out-of-range requests of the last stages, before the ring is reused
 
   // Epilogue.  32x32 accumulator layout: lane holds column (lane & 31) and rows

@@ -236,10 +236,11 @@ __device__ inline void dma_one(__amdgpu_buffer_rsrc_t rsrc, uint32_t lds_stage_a
   const uint32_t lds_addr = lds_stage_addr + wave_off + q * kThreads * 16;
   // Issued as inline assembly so the compiler does not add its own wait for the DMA
   // before every LDS read; completion is tracked explicitly with wait_vmcnt.  M0 (the
-  // DMA's LDS address) is saved and restored around the load.
+  // DMA's LDS address) is saved and restored around the load; an LDS DMA needs one wait
+  // state after an SALU write of M0.
   uint32_t m0_save;
   asm volatile(
-      "s_mov_b32 %[sv], m0\n\ts_mov_b32 m0, %[la]\n\t"
+      "s_mov_b32 %[sv], m0\n\ts_mov_b32 m0, %[la]\n\ts_nop 0\n\t"
       "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\ts_mov_b32 m0, %[sv]"
       : [sv] "=&s"(m0_save)
       : [la] "s"(lds_addr), [vo] "v"(vo), [rs] "s"(rsrc)

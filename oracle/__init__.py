@@ -23,9 +23,9 @@ _SRC = os.path.join(_HERE, "causal_oracle.c")
 _BUILD = os.path.join(_HERE, "_build")
 _LIB_PATH = os.path.join(_BUILD, "liboracle.so")
 
-MINK2_DIAMOND, MINK4_DIAMOND, DS4_SLAB = 0, 1, 2
-PLANES = {MINK2_DIAMOND: 2, MINK4_DIAMOND: 4, DS4_SLAB: 7}
-DIM = {MINK2_DIAMOND: 2, MINK4_DIAMOND: 4, DS4_SLAB: 4}
+MINK2_DIAMOND, MINK4_DIAMOND, DS4_SLAB, DS2_SLAB = 0, 1, 2, 3
+PLANES = {MINK2_DIAMOND: 2, MINK4_DIAMOND: 4, DS4_SLAB: 7, DS2_SLAB: 3}
+DIM = {MINK2_DIAMOND: 2, MINK4_DIAMOND: 4, DS4_SLAB: 4, DS2_SLAB: 2}
 
 _lib = None
 

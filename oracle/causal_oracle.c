@@ -13,7 +13,10 @@
  *   sprinkle      App. A, "Causal Set Sprinklings": 1+1 Minkowski diamond
  *                 (u, v uniform), 3+1 Minkowski diamond (here by rejection from the
  *                 bounding box), 3+1 de Sitter slab with spherical foliation
- *                 (density sec^4(eta) in conformal time, uniform on S^3).
+ *                 (density sec^4(eta) in conformal time, uniform on S^3), and the
+ *                 1+1 de Sitter slab of the benchmark section (Sec. 4.3: metric
+ *                 sec^2(eta)(-d eta^2 + d theta^2), density sec^2(eta), theta
+ *                 uniform on the circle).
  *   time order    Sec. 3.2 "Pairwise Relations": elements are labelled so that a
  *                 later index never precedes an earlier one.
  *   causal matrix Ch. 4 introduction: i and j are related when timelike
@@ -30,8 +33,10 @@
  * enumeration of all 2D orders on tiny sets, closed forms (chains, antichains,
  * disjoint chains), exact invariants (sum N_n = R, sum n N_n = sum indeg*outdeg),
  * the numpy C@C special case, statistical moments (ordering fractions 1/4 and
- * 1/10, 4D acceptance pi/24, conformal-time marginal), and exact rational
- * evaluation of the smeared sums.
+ * 1/10, 4D acceptance pi/24, conformal-time marginals, the 1+1 de Sitter relation
+ * probability E|d eta|/pi), symmetries of the cylinder (rotations and reflections
+ * of theta), transitivity of the relation, and exact rational evaluation of the
+ * smeared sums.
  *
  * Compiled with -O2 -fopenmp -ffp-contract=off: no fused multiply-add, so every
  * floating-point predicate is the exact sequence of IEEE operations written here.
@@ -43,7 +48,7 @@
 #include <omp.h>
 
 /* Region codes (same numeric values as the GPU library's public enumeration). */
-enum { OR_MINK2_DIAMOND = 0, OR_MINK4_DIAMOND = 1, OR_DS4_SLAB = 2 };
+enum { OR_MINK2_DIAMOND = 0, OR_MINK4_DIAMOND = 1, OR_DS4_SLAB = 2, OR_DS2_SLAB = 3 };
 
 /* ------------------------------------------------------------------------- */
 /* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014), as in the public-domain       */
@@ -97,6 +102,7 @@ int or_coord_planes(int region)
     case OR_MINK2_DIAMOND: return 2;  /* u, v                         */
     case OR_MINK4_DIAMOND: return 4;  /* t, x, y, z                   */
     case OR_DS4_SLAB:      return 7;  /* tan eta, cos eta, sin eta, n0..n3 on S^3 */
+    case OR_DS2_SLAB:      return 3;  /* tan eta, eta, theta                        */
     default:               return -1;
     }
 }
@@ -173,6 +179,25 @@ int or_sprinkle(int region, double eta0, uint64_t seed, int64_t n, double *coord
                 got++;
             }
         }
+    } else if (region == OR_DS2_SLAB) {
+        /* 1+1 de Sitter slab, spherical foliation, eta in [-eta0, eta0], theta on
+         * the circle.  The conformal-time density is proportional to sec^2(eta) =
+         * d tan(eta) / d eta, so x = tan(eta) is uniform on [-tan eta0, tan eta0]
+         * (computed exactly up to one rounding); eta = atan(x); theta = 2 pi w.
+         * Time order by x, which is monotone in eta. */
+        double X = tan(eta0);
+        double two_pi = 2.0 * M_PI;
+        uint64_t s = or_stream_key(seed, 4);
+        for (int64_t g = 0; g < n; g++) {
+            double u = or_unit(or_output(s, 2 * (uint64_t)g));
+            double w = or_unit(or_output(s, 2 * (uint64_t)g + 1));
+            double x = (2.0 * u - 1.0) * X;
+            raw[0 * n + g] = x;
+            raw[1 * n + g] = atan(x);
+            raw[2 * n + g] = two_pi * w;
+            keys[g].key = or_order_bits(x);
+            keys[g].gen = g;
+        }
     } else {
         /* 3+1 de Sitter slab, spherical foliation, eta in [-eta0, eta0]:
          * the conformal-time density is proportional to sec^4(eta).  With
@@ -245,6 +270,15 @@ static int or_related(int region, const double *c, int64_t n, int64_t i, int64_t
         double s = dx * dx + dy * dy;
         s = s + dz * dz;
         return dt * dt > s;
+    } else if (region == OR_DS2_SLAB) {
+        /* Timelike on the cylinder: the angular separation, measured the short way
+         * round, pi - |pi - |theta_i - theta_j||, is below the conformal-time
+         * separation eta_j - eta_i (strict on both counts). */
+        double deta = c[n + j] - c[n + i];
+        if (!(c[n + i] < c[n + j])) return 0;
+        double dth = fabs(c[2 * n + i] - c[2 * n + j]);
+        dth = M_PI - fabs(M_PI - dth);
+        return dth < deta;
     } else {
         /* Delta eta > great-circle angle  <=>  cos(Delta eta) < n_i . n_j, valid
          * because both angles lie in [0, pi] (Delta eta <= 2 eta0 < pi). */

@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-bitset", action="store_true",
                     help="skip the side legs (the other two counters)")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-ds2", action="store_true",
+                    help="skip the 1+1 de Sitter action series (the thesis's benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU work for the oracle sample")
@@ -108,7 +110,7 @@ def main():
     hist_ws = {c: torch.empty(L.cs_histogram_workspace_bytes(n, c), dtype=torch.uint8, device=dev)
                for c in COUNTERS.values()}
     main = COUNTERS[args.counter]
-    eta0 = W.DS_ETA0
+    eta0 = cfg.get("eta0", W.DS_ETA0)
 
     if args.copy_calibration_mb > 0:
         nb = args.copy_calibration_mb << 20
@@ -216,6 +218,10 @@ def main():
     if not args.no_batch and hasattr(L, "cs_batch_run"):
         from bench_batch import run_batch  # noqa: E402  (batch leg lives beside this file)
         out["batch"] = run_batch(cs, torch, dev, stream)
+
+    if not args.no_ds2:
+        from bench_ds2 import run_ds2  # noqa: E402  (lives beside this file)
+        out["ds2"] = run_ds2(cs, torch, dev, stream, main)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -58,9 +58,16 @@ typedef enum {
  *                     eta in [-eta0, eta0] with density ∝ sec^4(eta), uniform on S^3.
  *                     Planes: tan(eta), cos(eta), sin(eta), n0, n1, n2, n3 (unit vector).
  *                     i ≺ j iff eta_i < eta_j and cos(eta_j - eta_i) < n_i . n_j.
+ *   CS_DS2_SLAB       1+1 de Sitter slab, spherical foliation (Sec. 4.3, the benchmark
+ *                     of the action): metric sec^2(eta)(-d eta^2 + d theta^2), eta in
+ *                     [-eta0, eta0] with density ∝ sec^2(eta), theta uniform on [0, 2 pi).
+ *                     tan(eta) is uniform: x = (2u - 1) tan(eta0), eta = atan(x),
+ *                     theta = 2 pi w.  Planes: x = tan(eta), eta, theta.
+ *                     i ≺ j iff eta_i < eta_j and pi - |pi - |theta_i - theta_j|| <
+ *                     eta_j - eta_i (the angle measured the short way round).
  * Relations are strict: null-separated and equal-time pairs are unrelated.  All
  * predicates are evaluated in IEEE fp64 in the order written, without contraction. */
-enum { CS_MINK2_DIAMOND = 0, CS_MINK4_DIAMOND = 1, CS_DS4_SLAB = 2 };
+enum { CS_MINK2_DIAMOND = 0, CS_MINK4_DIAMOND = 1, CS_DS4_SLAB = 2, CS_DS2_SLAB = 3 };
 
 /* Interval counters (all three give identical, exact results). */
 enum {
@@ -72,7 +79,7 @@ enum {
                               n < 2^24 (CS_ERR_OVERFLOW otherwise)                        */
 };
 
-/* Number of fp64 coordinate planes of a region (2, 4 or 7); -1 if unknown. */
+/* Number of fp64 coordinate planes of a region (2, 4, 7 or 3); -1 if unknown. */
 int cs_coord_planes(int region);
 
 /* Row stride of the packed matrix in uint64 words: n rounded up to 512 bits. */

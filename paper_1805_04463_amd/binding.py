@@ -16,9 +16,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libcausal.so")
 
-CS_MINK2_DIAMOND, CS_MINK4_DIAMOND, CS_DS4_SLAB = 0, 1, 2
+CS_MINK2_DIAMOND, CS_MINK4_DIAMOND, CS_DS4_SLAB, CS_DS2_SLAB = 0, 1, 2, 3
 CS_COUNT_BITSET, CS_COUNT_MFMA, CS_COUNT_MFMA_FP4 = 0, 1, 2
-REGION_DIM = {CS_MINK2_DIAMOND: 2, CS_MINK4_DIAMOND: 4, CS_DS4_SLAB: 4}
+REGION_DIM = {CS_MINK2_DIAMOND: 2, CS_MINK4_DIAMOND: 4, CS_DS4_SLAB: 4, CS_DS2_SLAB: 2}
 
 SYMBOLS = [
     "cs_coord_planes", "cs_ld_words", "cs_status_string", "cs_sprinkle_workspace_bytes",

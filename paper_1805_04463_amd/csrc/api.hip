@@ -53,7 +53,8 @@ cs_status cs_sprinkle(int region, double eta0, uint64_t seed, int64_t n, double*
   cs_status s = check_n(n);
   if (s != CS_OK) return s;
   if (!coords || !workspace) return CS_ERR_INVALID_ARG;
-  if (region == CS_DS4_SLAB && !(eta0 > 0.0 && eta0 < 1.5707963267948966))
+  if ((region == CS_DS4_SLAB || region == CS_DS2_SLAB) &&
+      !(eta0 > 0.0 && eta0 < 1.5707963267948966))
     return CS_ERR_INVALID_ARG;
   if (workspace_bytes < sprinkle_ws_bytes(region, n)) return CS_ERR_WORKSPACE;
   return launch_sprinkle(region, eta0, seed, n, coords, workspace, as_stream(stream));

@@ -32,6 +32,10 @@ template <>
 struct Pt<CS_DS4_SLAB> {
   double x, c, s, n0, n1, n2, n3;
 };
+template <>
+struct Pt<CS_DS2_SLAB> {
+  double eta, th;
+};
 
 __device__ inline Pt<CS_MINK2_DIAMOND> load_pt(const double* c, int64_t n, int64_t i,
                                                Pt<CS_MINK2_DIAMOND>*) {
@@ -44,6 +48,11 @@ __device__ inline Pt<CS_MINK4_DIAMOND> load_pt(const double* c, int64_t n, int64
 __device__ inline Pt<CS_DS4_SLAB> load_pt(const double* c, int64_t n, int64_t i,
                                           Pt<CS_DS4_SLAB>*) {
   return {c[i], c[n + i], c[2 * n + i], c[3 * n + i], c[4 * n + i], c[5 * n + i], c[6 * n + i]};
+}
+
+__device__ inline Pt<CS_DS2_SLAB> load_pt(const double* c, int64_t n, int64_t i,
+                                          Pt<CS_DS2_SLAB>*) {
+  return {c[n + i], c[2 * n + i]};
 }
 
 // a ≺ b for a earlier than b in time order.
@@ -66,6 +75,14 @@ __device__ inline bool precedes(const Pt<CS_DS4_SLAB>& a, const Pt<CS_DS4_SLAB>&
   dot = __dadd_rn(dot, __dmul_rn(a.n2, b.n2));
   dot = __dadd_rn(dot, __dmul_rn(a.n3, b.n3));
   return (a.x < b.x) & (cd < dot);
+}
+__device__ inline bool precedes(const Pt<CS_DS2_SLAB>& a, const Pt<CS_DS2_SLAB>& b) {
+  // The angular separation the short way round, pi - |pi - |theta_a - theta_b||, below
+  // the conformal-time separation (fabs is exact; pi is the double nearest pi).
+  const double pi = 3.141592653589793;
+  double dth = fabs(__dsub_rn(a.th, b.th));
+  dth = __dsub_rn(pi, fabs(__dsub_rn(pi, dth)));
+  return (a.eta < b.eta) & (dth < __dsub_rn(b.eta, a.eta));
 }
 
 constexpr int kWavesPerBlock = 4;
@@ -173,6 +190,7 @@ cs_status launch_causal_matrix(int region, const double* coords, int64_t n, uint
     case CS_MINK2_DIAMOND: return launch_build<CS_MINK2_DIAMOND>(coords, n, bits, ld, st);
     case CS_MINK4_DIAMOND: return launch_build<CS_MINK4_DIAMOND>(coords, n, bits, ld, st);
     case CS_DS4_SLAB: return launch_build<CS_DS4_SLAB>(coords, n, bits, ld, st);
+    case CS_DS2_SLAB: return launch_build<CS_DS2_SLAB>(coords, n, bits, ld, st);
     default: return CS_ERR_UNSUPPORTED;
   }
 }

@@ -31,7 +31,13 @@ __host__ __device__ inline uint64_t sm_stream_key(uint64_t seed, uint64_t stream
 __device__ inline double unit53(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
 
 // Streams of the generator per region.
-enum : uint64_t { kStreamMink2 = 0, kStreamMink4 = 1, kStreamDsTime = 2, kStreamDsSphere = 3 };
+enum : uint64_t {
+  kStreamMink2 = 0,
+  kStreamMink4 = 1,
+  kStreamDsTime = 2,
+  kStreamDsSphere = 3,
+  kStreamDs2 = 4
+};
 
 // Rejection sampling of the S^3 direction gives up after this many tries (probability
 // 0.69^4096: never reached in practice, but every loop has a bound).
@@ -58,6 +64,7 @@ inline int coord_planes(int region) {
     case CS_MINK2_DIAMOND: return 2;
     case CS_MINK4_DIAMOND: return 4;
     case CS_DS4_SLAB: return 7;
+    case CS_DS2_SLAB: return 3;
     default: return -1;
   }
 }

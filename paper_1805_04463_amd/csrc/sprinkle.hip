@@ -211,6 +211,32 @@ __global__ void k_pad_keys(int64_t n, int64_t P, uint64_t* __restrict__ keys,
 }
 
 // ---------------------------------------------------------------------------
+// 1+1 de Sitter slab: the density sec^2(eta) = d tan(eta)/d eta makes x = tan(eta)
+// uniform, x = (2u - 1) tan(eta0) (one rounding); eta = atan(x); theta = 2 pi w.
+// Sorted by x, which orders the points by eta.
+// ---------------------------------------------------------------------------
+__global__ void k_sprinkle_ds2(uint64_t skey, double X, int64_t n, int64_t P,
+                               double* __restrict__ raw, uint64_t* __restrict__ keys,
+                               uint32_t* __restrict__ gens) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= P) return;
+  if (g >= n) {
+    keys[g] = ~0ull;
+    gens[g] = 0xFFFFFFFFu;
+    return;
+  }
+  const double two_pi = 2.0 * 3.141592653589793;  // twice the double nearest pi (exact)
+  double u = unit53(sm_output(skey, 2 * (uint64_t)g));
+  double w = unit53(sm_output(skey, 2 * (uint64_t)g + 1));
+  double x = __dmul_rn(__dsub_rn(__dmul_rn(2.0, u), 1.0), X);
+  raw[g] = x;
+  raw[n + g] = atan(x);
+  raw[2 * n + g] = __dmul_rn(two_pi, w);
+  keys[g] = order_bits(x);
+  gens[g] = (uint32_t)g;
+}
+
+// ---------------------------------------------------------------------------
 // 3+1 de Sitter slab: x = tan(eta) from the inverse CDF of (1 + x^2) dx,
 // x = 2 sinh(asinh(3y/2)/3); direction on S^3 by cube rejection, normalised.
 // ---------------------------------------------------------------------------
@@ -421,6 +447,10 @@ cs_status launch_sprinkle(int region, double eta0, uint64_t seed, int64_t n, dou
                          n, P, w.keys, w.gens);
       CS_LAUNCH_CHECK();
     }
+  } else if (region == CS_DS2_SLAB) {
+    hipLaunchKernelGGL(k_sprinkle_ds2, dim3(gridP), dim3(kBlock), 0, st,
+                       sm_stream_key(seed, kStreamDs2), tan(eta0), n, P, w.raw, w.keys, w.gens);
+    CS_LAUNCH_CHECK();
   } else {
     hipLaunchKernelGGL(k_sprinkle_ds4, dim3(gridP), dim3(kBlock), 0, st,
                        sm_stream_key(seed, kStreamDsTime), sm_stream_key(seed, kStreamDsSphere),

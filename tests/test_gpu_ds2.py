@@ -1,0 +1,116 @@
+"""GPU parity on the 1+1 de Sitter slab of the thesis's action benchmark.
+
+Sprinkle: tan(eta) and theta come from exact operations (one rounding each) and match
+the oracle bit for bit, which also fixes the time order; eta = atan(tan eta) may
+differ by an ulp between the device and host libraries, so the matrix is checked on a
+shared coordinate buffer (the oracle's, then the device's).  Matrix and N_n are then
+bit-exact for every counter and the actions agree to 1e-12.  At N = 131072 the
+matrix is checked on sampled rows and N_n through the exact invariants sum N_n = R and
+sum n N_n = sum indeg * outdeg.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+ETA0, EPS = W.DS2_ETA0, W.DS2_EPS
+
+
+@pytest.fixture(scope="module")
+def cs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_04463_amd as cs
+    cs.lib()
+    return cs
+
+
+def host_u64(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("n", [2, 3, 100, 5000])
+def test_ds2_sprinkle(cs, orc, n):
+    want = orc.sprinkle(W.DS2_SLAB, n, 101, eta0=ETA0)
+    got = cs.cs_sprinkle(W.DS2_SLAB, n, 101, eta0=ETA0).cpu().numpy()
+    assert np.array_equal(got[0], want[0])          # tan(eta): exact, and the time order
+    assert np.array_equal(got[2], want[2])          # theta: exact
+    assert np.all(np.abs(got[1] - want[1]) <= 2 * np.spacing(np.abs(want[1])))
+
+
+@pytest.mark.parametrize("n", [700, 4096, 9001])
+def test_ds2_matrix_counts_actions(cs, orc, n):
+    coords = orc.sprinkle(W.DS2_SLAB, n, 102, eta0=ETA0)
+    want = orc.causal_matrix(W.DS2_SLAB, coords)
+    b = cs.cs_causal_matrix(W.DS2_SLAB, torch.from_numpy(coords).cuda())
+    assert np.array_equal(host_u64(b), want)
+    hist, _ = orc.histogram_fast(want, n)
+    acts = {e: orc.action(hist, n, 2, e)[0] for e in (0.0, EPS, 0.1)}
+    for counter in (cs.CS_COUNT_BITSET, cs.CS_COUNT_MFMA, cs.CS_COUNT_MFMA_FP4):
+        h = cs.cs_interval_histogram(b, n, counter)
+        assert np.array_equal(host_u64(h), hist), counter
+        for e, a in acts.items():
+            got = cs.cs_action(h, n, 2, e).item()
+            assert abs(got - a) <= 1e-12 * max(abs(a), 1.0), (counter, e, got, a)
+
+
+def test_ds2_whole_path_n16384(cs, orc):
+    n, seed = 16384, W.DS2_SEEDS[0]
+    c = cs.cs_sprinkle(W.DS2_SLAB, n, seed, eta0=ETA0)
+    coords = c.cpu().numpy()
+    b = cs.cs_causal_matrix(W.DS2_SLAB, c)
+    want = orc.causal_matrix(W.DS2_SLAB, coords)
+    assert np.array_equal(host_u64(b), want)
+    hist, _ = orc.histogram_fast(want, n)
+    h = cs.cs_interval_histogram(b, n, cs.CS_COUNT_MFMA_FP4)
+    assert np.array_equal(host_u64(h), hist)
+    a = orc.action(hist, n, 2, EPS)[0]
+    assert abs(cs.cs_action(h, n, 2, EPS).item() - a) <= 1e-12 * max(abs(a), 1.0)
+
+
+def test_ds2_n131072(cs, orc):
+    from test_gpu_fullsize import degree_moments
+    cfg = W.WORKLOADS["ds2_n131072"]
+    n, seed = cfg["n"], cfg["seed"]
+    c = cs.cs_sprinkle(W.DS2_SLAB, n, seed, eta0=ETA0)
+    coords = c.cpu().numpy()
+    want_c = orc.sprinkle(W.DS2_SLAB, n, seed, eta0=ETA0)
+    assert np.array_equal(coords[0], want_c[0]) and np.array_equal(coords[2], want_c[2])
+    b = cs.cs_causal_matrix(W.DS2_SLAB, c)
+    got = host_u64(b)
+    rng = np.random.default_rng(7)
+    rows = np.unique(np.concatenate([np.arange(64), rng.integers(0, n, 192), np.arange(n - 64, n)]))
+    assert np.array_equal(got[rows], orc.causal_rows(W.DS2_SLAB, coords, rows))
+    rel, c3 = degree_moments(got, n)
+    del got
+    hf = host_u64(cs.cs_interval_histogram(b, n, cs.CS_COUNT_MFMA_FP4)).copy()
+    hm = host_u64(cs.cs_interval_histogram(b, n, cs.CS_COUNT_MFMA)).copy()
+    assert np.array_equal(hf, hm)
+    assert int(hf.sum()) == rel
+    assert int((np.arange(n - 1, dtype=np.uint64) * hf).sum()) == c3
+
+
+def test_ds2_action_approaches_einstein_hilbert(cs):
+    """Sec. 4.3: over ten graphs the mean smeared action approaches S_EH = 4 pi tan(eta0),
+    and its standard deviation grows with N because eps is held fixed."""
+    import math
+    target = 4 * math.pi * math.tan(ETA0)
+    stats = {}
+    for n in (1 << 15, 1 << 17):
+        v = []
+        for seed in W.DS2_SEEDS:
+            c = cs.cs_sprinkle(W.DS2_SLAB, n, seed, eta0=ETA0)
+            b = cs.cs_causal_matrix(W.DS2_SLAB, c)
+            h = cs.cs_interval_histogram(b, n, cs.CS_COUNT_MFMA_FP4)
+            v.append(cs.cs_action(h, n, 2, EPS).item())
+            del b
+        v = np.array(v)
+        stats[n] = (v.mean(), v.std(ddof=1))
+    mean, sd = stats[1 << 17]
+    assert abs(mean - target) < 3 * sd / math.sqrt(len(W.DS2_SEEDS)), (mean, sd, target)
+    assert stats[1 << 17][1] > stats[1 << 15][1]

@@ -69,6 +69,8 @@ def lib():
         L.or_histogram_fast_rows.argtypes = [p, i64, i64, p, p, i64]
         L.or_histogram_fast_rows.restype = i64
         L.or_pair_interval.argtypes = [p, i64, i64, i64]
+        L.or_dalembertian.restype = c_int
+        L.or_dalembertian.argtypes = [p, i64, i64, c_int, dbl, p, p, p, p]
         L.or_pair_interval.restype = i64
         L.or_degrees.argtypes = [p, i64, i64, p, p, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         L.or_degrees.restype = c_int
@@ -185,6 +187,20 @@ def action(hist: np.ndarray, n: int, dim: int, eps: float = 0.0):
     if lib().or_action(_ptr(hist), n, dim, eps, ctypes.byref(out), ctypes.byref(kap)) != 0:
         raise ValueError("or_action failed")
     return out.value, kap.value
+
+
+def dalembertian(bits: np.ndarray, n: int, dim: int, ell: float, phi: np.ndarray):
+    """B^(d+1) phi for every element (Sec. 4.1), with the summand count and the sum of
+    absolute summands of each element: (out, terms, abs_sum)."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    assert phi.shape == (n,)
+    out = np.empty(n, dtype=np.float64)
+    terms = np.empty(n, dtype=np.int64)
+    mag = np.empty(n, dtype=np.float64)
+    if lib().or_dalembertian(_ptr(bits), n, bits.shape[1], dim, ell, _ptr(phi), _ptr(out),
+                             _ptr(terms), _ptr(mag)) != 0:
+        raise ValueError("or_dalembertian failed")
+    return out, terms, mag
 
 
 def smear_weight(dim: int, m: int, eps: float) -> float:

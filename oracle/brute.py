@@ -63,3 +63,20 @@ def local_integer(hist, n, dim):
     if dim == 2:
         return n - 2 * h[0] + 4 * h[1] - 2 * h[2]
     return n - h[0] + 9 * h[1] - 16 * h[2] + 8 * h[3]
+
+
+def dalembertian_2d_exact(n, rel, phi, ell2: Fraction):
+    """B^(1+1) phi(j) = (2 / ell^2) [-phi(j) + 2 (sum_{L1} - 2 sum_{L2} + sum_{L3})] in exact
+    rationals, with L_m(j) found by enumerating each Alexandroff set (Sec. 4.1)."""
+    coef = {0: 2, 1: -4, 2: 2}
+    out = []
+    for j in range(n):
+        acc = -Fraction(phi[j])
+        for i in range(n):
+            if (i, j) not in rel:
+                continue
+            inside = sum(1 for k in range(n) if (i, k) in rel and (k, j) in rel)
+            if inside in coef:
+                acc += coef[inside] * Fraction(phi[i])
+        out.append(2 * acc / ell2)
+    return out

@@ -28,6 +28,8 @@
  *                 + popcount over the columns strictly between i and j.
  *   action        Sec. 4.2: local BD actions S^(1+1), S^(3+1) and their smeared
  *                 forms S_eps with the smearing functions f_2 and f_4.
+ *   d'Alembertian Sec. 4.1, eqs. b2d_local and b4d_local: B phi(j) from the sums of
+ *                 phi over the inclusive order intervals L_1 .. L_4 of each element.
  *
  * Parity pins (see tests/test_oracle_*.py): generator test vector, brute-force
  * enumeration of all 2D orders on tiny sets, closed forms (chains, antichains,
@@ -567,3 +569,51 @@ double or_smear_weight(int dim, int64_t m, double eps)
 }
 
 int or_max_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------------- */
+/* Discrete d'Alembertian (Sec. 4.1, eqs. b2d_local and b4d_local)            */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * B phi(j) = (K / ell^2) [ -phi(j) + sum_m c_m sum_{i in L_m(j)} phi(i) ] for every j,
+ * with L_m(j) = { i ≺ j : exactly m-1 elements strictly between i and j }:
+ *   1+1: K = 2,          c = ( 2, -4,  2)      (the bracket 2 (L1 - 2 L2 + L3))
+ *   3+1: K = 4/sqrt(6),  c = ( 1, -9, 16, -8)
+ * Sums and constants in __float128, one rounding at the end.  Optional outputs for
+ * error bounds of other summation orders: terms[j] = 1 + |L_1(j)| + ... (the number
+ * of summands) and abs_sum[j] = |phi(j)| + sum_m |c_m| sum_{i in L_m(j)} |phi(i)|.
+ * Returns 0, or -1 on bad arguments.
+ */
+int or_dalembertian(const uint64_t *bits, int64_t n, int64_t ld, int dim, double ell,
+                    const double *phi, double *out, int64_t *terms, double *abs_sum)
+{
+    q_t K;
+    int layers;
+    q_t c[4];
+    if (dim == 2) {
+        K = 2; layers = 3; c[0] = 2; c[1] = -4; c[2] = 2; c[3] = 0;
+    } else if (dim == 4) {
+        K = 4 / q_sqrt(6); layers = 4; c[0] = 1; c[1] = -9; c[2] = 16; c[3] = -8;
+    } else {
+        return -1;
+    }
+    if (n < 1 || ld * 64 < n || !(ell > 0.0)) return -1;
+    const q_t scale = K / ((q_t)ell * (q_t)ell);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < n; j++) {
+        q_t sum = -(q_t)phi[j], mag = fabs(phi[j]);
+        int64_t cnt = 1;
+        for (int64_t i = 0; i < j; i++) {
+            if (!or_bit(bits, ld, j, i)) continue;      /* i ≺ j (i earlier) */
+            int64_t m = or_pair_interval(bits, ld, i, j); /* |L| index m+1 */
+            if (m >= layers) continue;
+            sum += c[m] * (q_t)phi[i];
+            mag += fabs((double)c[m]) * fabs(phi[i]);
+            cnt++;
+        }
+        out[j] = (double)(scale * sum);
+        if (terms) terms[j] = cnt;
+        if (abs_sum) abs_sum[j] = (double)mag;
+    }
+    return 0;
+}

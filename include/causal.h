@@ -133,6 +133,31 @@ cs_status cs_interval_histogram(const uint64_t *bits, int64_t n, int64_t ld_word
                                 uint64_t *hist, void *workspace, size_t workspace_bytes,
                                 void *stream);
 
+/* Device workspace needed by cs_dalembertian, in bytes (0 for a bad n or counter). */
+size_t cs_dalembertian_workspace_bytes(int64_t n, int counter);
+
+/*
+ * Discrete d'Alembertian of a scalar field on the causal set (Sec. 4.1, eqs. b2d_local and
+ * b4d_local), for every element j:
+ *   B phi(j) = (K / ell^2) [ -phi(j) + sum_m c_m sum_{i in L_m(j)} phi(i) ],
+ *   L_m(j) = { i ≺ j with exactly m-1 elements strictly between i and j },
+ *   dim = 2: K = 2,          (c_1, c_2, c_3)      = (2, -4, 2)
+ *   dim = 4: K = 4/sqrt(6),  (c_1, c_2, c_3, c_4) = (1, -9, 16, -8).
+ *   bits     device, the matrix from cs_causal_matrix (n rows, ld_words stride).
+ *   ell      discreteness scale (> 0), nu^(-1/(d+1)) for sprinkling density nu.
+ *   counter  CS_COUNT_MFMA or CS_COUNT_MFMA_FP4 (the interval sizes come from the same
+ *            tiles as cs_interval_histogram; the bitset counter gives CS_ERR_UNSUPPORTED).
+ *   phi      device, n doubles (time-ordered like the points).
+ *   out      device, n doubles, overwritten.
+ *   workspace device, at least cs_dalembertian_workspace_bytes(n, counter) bytes.
+ * The sums over L_m(j) are accumulated in fp64 by atomic adds in an order that varies
+ * between runs, so each out[j] is exact up to the rounding of a sum of its summands.
+ * Same limits as cs_interval_histogram for the MFMA counters.
+ */
+cs_status cs_dalembertian(const uint64_t *bits, int64_t n, int64_t ld_words, int dim, double ell,
+                          int counter, const double *phi, double *out, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
 /*
  * Benincasa-Dowker action from the abundances (l = l_p).
  *   dim = 2: eps == 0: S = 2 (N - 2N_0 + 4N_1 - 2N_2)

@@ -26,6 +26,7 @@ SYMBOLS = [
     "cs_action", "cs_batch_plan", "cs_batch_workspace_bytes", "cs_batch_hist_len",
     "cs_batch_hist_offset", "cs_batch_run", "cs_batch_free", "cs_batch_graph_create",
     "cs_batch_graph_launch", "cs_batch_graph_destroy", "cs_autotune", "cs_measure_mfma_peak",
+    "cs_dalembertian_workspace_bytes", "cs_dalembertian",
 ]
 
 
@@ -55,6 +56,8 @@ def lib():
             "cs_histogram_workspace_bytes": (sz, [i64, c_int]),
             "cs_interval_histogram": (c_int, [p, i64, i64, c_int, p, p, sz, p]),
             "cs_action": (c_int, [p, i64, c_int, dbl, p, p]),
+            "cs_dalembertian_workspace_bytes": (sz, [i64, c_int]),
+            "cs_dalembertian": (c_int, [p, i64, i64, c_int, dbl, c_int, p, p, p, sz, p]),
             "cs_batch_plan": (c_int, [i64, p, c_int, c_int, p, ctypes.c_char_p, ctypes.POINTER(p)]),
             "cs_batch_workspace_bytes": (sz, [p]),
             "cs_batch_hist_len": (i64, [p]),
@@ -152,6 +155,20 @@ def cs_interval_histogram(bits: torch.Tensor, n: int, counter: int = CS_COUNT_MF
                                        ws.numel(), _stream(stream)), "cs_interval_histogram")
     hist._cs_keepalive = ws
     return hist
+
+
+def cs_dalembertian(bits: torch.Tensor, n: int, dim: int, ell: float, phi: torch.Tensor,
+                    counter: int = CS_COUNT_MFMA_FP4, out: torch.Tensor | None = None,
+                    workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """B^(d+1) phi for every element as a float64 device tensor (phi: n float64 on device)."""
+    ld = bits.shape[1]
+    o = out if out is not None else torch.empty(n, dtype=torch.float64, device=_dev())
+    ws_bytes = lib().cs_dalembertian_workspace_bytes(n, counter)
+    ws = workspace if workspace is not None else _u8_workspace(max(ws_bytes, 1))
+    _check(lib().cs_dalembertian(_ptr(bits), n, ld, dim, float(ell), counter, _ptr(phi), _ptr(o),
+                                 _ptr(ws), ws.numel(), _stream(stream)), "cs_dalembertian")
+    o._cs_keepalive = ws
+    return o
 
 
 def cs_action(hist: torch.Tensor, n: int, dim: int, eps: float = 0.0,

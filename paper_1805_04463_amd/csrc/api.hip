@@ -88,6 +88,27 @@ cs_status cs_interval_histogram(const uint64_t* bits, int64_t n, int64_t ld_word
   return launch_histogram(bits, n, ld_words_, counter, hist, workspace, as_stream(stream));
 }
 
+size_t cs_dalembertian_workspace_bytes(int64_t n, int counter) {
+  if (check_n(n) != CS_OK || (counter != CS_COUNT_MFMA && counter != CS_COUNT_MFMA_FP4)) return 0;
+  return field_ws_bytes(n, counter);
+}
+
+cs_status cs_dalembertian(const uint64_t* bits, int64_t n, int64_t ld_words_, int dim, double ell,
+                          int counter, const double* phi, double* out, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+  if (dim != 2 && dim != 4) return CS_ERR_UNSUPPORTED;
+  if (counter != CS_COUNT_MFMA && counter != CS_COUNT_MFMA_FP4) return CS_ERR_UNSUPPORTED;
+  cs_status s = check_n(n);
+  if (s != CS_OK) return s;
+  if (!bits || !phi || !out || !workspace || ld_words_ < ld_words(n)) return CS_ERR_INVALID_ARG;
+  if (!(ell > 0.0) || !isfinite(ell)) return CS_ERR_INVALID_ARG;
+  if (counter == CS_COUNT_MFMA_FP4 && n >= (int64_t)1 << 24) return CS_ERR_OVERFLOW;
+  if (ld_words_ > kMaxMfmaLd) return CS_ERR_OVERFLOW;
+  if (workspace_bytes < field_ws_bytes(n, counter)) return CS_ERR_WORKSPACE;
+  return launch_dalembertian(bits, n, ld_words_, counter, dim, ell, phi, out, workspace,
+                             as_stream(stream));
+}
+
 cs_status cs_action(const uint64_t* hist, int64_t n, int dim, double eps, double* out,
                     void* stream) {
   if (dim != 2 && dim != 4) return CS_ERR_UNSUPPORTED;

@@ -101,6 +101,9 @@ cs_status launch_sprinkle(int region, double eta0, uint64_t seed, int64_t n, dou
 cs_status launch_causal_matrix(int region, const double* coords, int64_t n, uint64_t* bits,
                                int64_t ld, hipStream_t st);
 size_t histogram_ws_bytes(int64_t n, int counter);
+size_t field_ws_bytes(int64_t n, int counter);
+cs_status launch_dalembertian(const uint64_t* bits, int64_t n, int64_t ld, int counter, int dim,
+                              double ell, const double* phi, double* out, void* ws, hipStream_t st);
 cs_status launch_histogram(const uint64_t* bits, int64_t n, int64_t ld, int counter,
                            uint64_t* hist, void* ws, hipStream_t st);
 cs_status launch_action(const uint64_t* hist, int64_t n, int dim, double eps, double* out,

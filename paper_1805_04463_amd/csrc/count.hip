@@ -184,12 +184,20 @@ __device__ inline int64_t next_tile(unsigned int* counter, int* slot) {
   return *slot;
 }
 
+// Arguments of the d'Alembertian epilogue: out[j] accumulates sum_m c_m sum_{L_m(j)} phi(i).
+struct FieldArgs {
+  const double* phi;
+  double* out;
+  double c0, c1, c2, c3;      // c_m for pairs with m interior elements (0 past the last layer)
+};
+
 struct TileArgs {
   const uint32_t* S32;        // instance matrix, as 32-bit words
   int64_t ld32;               // row stride in 32-bit words
   int64_t n;                  // points of the instance
   int64_t I0, J0;             // first row / first column of the output tile
   unsigned long long* hist;   // instance histogram (n-1 bins)
+  FieldArgs f;                // d'Alembertian epilogue only
 };
 
 // ===========================================================================
@@ -443,10 +451,12 @@ __device__ inline void mfma_stage(Acc (&acc)[WM][WM], uint4 (&aw)[2][WM], uint4 
   });
 }
 
-template <int WM, int HB, bool FP4 = false>
+// EPI 0: histogram of the interval sizes of the related pairs.  EPI 1: d'Alembertian
+// sums, per column j, of c_m phi(i) over the related pairs (i, j) with m interior elements.
+template <int WM, int HB, bool FP4 = false, int EPI = 0>
 __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& ta, uint32_t* ring,
                                                                 uint32_t* rel, uint32_t* lds_hist,
-                                                                uint32_t& tmax) {
+                                                                uint32_t& tmax, double* phis) {
   using Acc = typename std::conditional<FP4, v16f, v16i>::type;
   constexpr int BM = 2 * WM * 32;
   constexpr int kStage = BM * kMStageU32;      // one panel stage, uint32 words
@@ -512,6 +522,9 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
       return false;
     }
   }
+  if constexpr (EPI == 1) {  // phi of the tile's rows, read by the epilogue
+    for (int r = threadIdx.x; r < BM; r += kThreads) phis[r] = I0 + r < n ? ta.f.phi[I0 + r] : 0.0;
+  }
   // Only the first and the last stage overlap a diagonal block (the A rows' block lies
   // in stage 0, the B rows' block in the last stage); both are masked in LDS before they
   // are read, the first here, the last halfway through the stage before it.
@@ -568,6 +581,7 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   stage(std::integral_constant<int, 2>{}, s);
   wait_vmcnt<0>();  // the out-of-range requests of the last stages, before the ring is reused
 
+  if constexpr (EPI == 0) {
   // Epilogue.  32x32 accumulator layout: lane holds column (lane & 31) and rows
   // 8*(e/4) + 4*(lane/32) + (e%4) for e = 0..15.  Branch-free binning: key = the pair's
   // count if it is related, else 0xFFFFFFFF (unrelated pairs all have count 0).  Every
@@ -603,6 +617,34 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
             atomicAdd(ta.hist + bin, 1ull);
         }
       }
+    }
+  }
+  } else {
+    // d'Alembertian epilogue: per column j of this lane, sum c_m phi(i) over the lane's
+    // related rows i with m interior elements (m < 4; unrelated pairs have key 0xFFFFFFFF);
+    // the two half-waves hold the same columns and are combined by a lane exchange, and
+    // each wave row adds its partial sums to out[j] with one fp64 atomic per column.
+#pragma unroll
+    for (int nb = 0; nb < WM; ++nb) {
+      double part = 0.0;
+#pragma unroll
+      for (int mb = 0; mb < WM; ++mb) {
+        const uint32_t w = rel[((wave * WM + nb) * WM + mb) * 32 + l32] >> (4 * hsel);
+        if (!__ballot(w != 0u)) continue;
+        const uint32_t wn = ~w;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int sh = (e >> 2) * 8 + (e & 3);
+          const uint32_t key = (uint32_t)acc[mb][nb][e] | (uint32_t)(-(int32_t)((wn >> sh) & 1u));
+          const double c = key == 0u ? ta.f.c0 : key == 1u ? ta.f.c1 : key == 2u ? ta.f.c2
+                         : key == 3u ? ta.f.c3 : 0.0;
+          const int r = wr * (WM * 32) + mb * 32 + (e >> 2) * 8 + hsel * 4 + (e & 3);
+          part = __fma_rn(c, phis[r], part);
+        }
+      }
+      part += __shfl_xor(part, 32);
+      const int64_t j = J0 + wc * (WM * 32) + nb * 32 + l32;
+      if (hsel == 0 && part != 0.0 && j < n) atomicAdd(ta.f.out + j, part);
     }
   }
   return true;
@@ -781,6 +823,7 @@ template <int BM, int HB>
 struct MfmaLds {
   uint32_t ring[MRing<BM>::value * 2 * BM * kMStageU32] __attribute__((aligned(16)));
   uint32_t rel[BM * BM / 32];  // relation bits of the current tile's pairs (i < j)
+  double phis[BM];             // phi of the tile's rows (d'Alembertian epilogue)
   uint32_t hist[HB + 64];      // bins, then one spare word per lane (never flushed)
   uint32_t maxbin;
   int slot;
@@ -798,18 +841,20 @@ struct BitsetLds {
   int slot;
 };
 
-template <int WM, bool FP4>
+template <int WM, bool FP4, int EPI>
 __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __restrict__ S,
                                                             int64_t n, int64_t ld,
                                                             unsigned long long* __restrict__ hist,
-                                                            unsigned int* __restrict__ counter) {
+                                                            unsigned int* __restrict__ counter,
+                                                            FieldArgs f) {
   constexpr int BM = 2 * WM * 32, HB = kBinsSingle;
   __shared__ MfmaLdsSched<BM, HB> L;  // 96 KiB ring + 32 KiB bins + 16 KiB table at WM = 4
   const int64_t T = ceil_div(n, BM);
-  for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
+  if constexpr (EPI == 0)
+    for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
   uint32_t tmax = 0;
   int64_t pairs_in_lds = 0;
-  TileArgs ta{(const uint32_t*)S, 2 * ld, n, 0, 0, hist};
+  TileArgs ta{(const uint32_t*)S, 2 * ld, n, 0, 0, hist, f};
   // Rectangle queues per XCD while the table fits; beyond that (very large n) one queue,
   // longest K-range first.
   const bool rect = rect_sched_fits(T);
@@ -833,15 +878,16 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
       if (t >= ntiles) break;
       tile_of(t, T, &I, &J);
     }
-    if (pairs_in_lds > (1ll << 31) - (int64_t)BM * BM) {  // keep uint32 LDS bins exact
+    if (EPI == 0 && pairs_in_lds > (1ll << 31) - (int64_t)BM * BM) {  // uint32 LDS bins exact
       flush_hist<HB>(L.hist, hist, n - 1, tmax, &L.maxbin);
       pairs_in_lds = 0;
     }
     ta.I0 = I * BM;
     ta.J0 = J * BM;
-    if (mfma_tile<WM, HB, FP4>(ta, L.ring, L.rel, L.hist, tmax)) pairs_in_lds += (int64_t)BM * BM;
+    if (mfma_tile<WM, HB, FP4, EPI>(ta, L.ring, L.rel, L.hist, tmax, L.phis))
+      pairs_in_lds += (int64_t)BM * BM;
   }
-  flush_hist<HB>(L.hist, hist, n - 1, tmax, &L.maxbin);
+  if constexpr (EPI == 0) flush_hist<HB>(L.hist, hist, n - 1, tmax, &L.maxbin);
 }
 
 __global__ __launch_bounds__(kThreads, 2) void k_count_bitset(const uint64_t* __restrict__ S,
@@ -921,7 +967,7 @@ __global__ __launch_bounds__(kThreads, MODE == 4 ? 1 : 2) void k_count_batch(
       if constexpr (MODE == 0)
         bitset_tile<HB>(ta, L.As, L.Bs, L.hist, tmax);
       else
-        mfma_tile<MODE, HB, FP4>(ta, L.ring, L.rel, L.hist, tmax);
+        mfma_tile<MODE, HB, FP4>(ta, L.ring, L.rel, L.hist, tmax, nullptr);
     }
   }
   if (cur >= 0) flush_hist<HB>(L.hist, ta.hist, ta.n - 1, tmax, &L.maxbin);
@@ -956,16 +1002,23 @@ cs_status launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream_
 
 size_t histogram_ws_bytes(int64_t, int) { return 256; }
 
-template <int WM, bool FP4>
+template <int WM, bool FP4, int EPI = 0>
 cs_status launch_mfma(const uint64_t* bits, int64_t n, int64_t ld, uint64_t* hist,
-                      unsigned int* ctr, hipStream_t st) {
+                      unsigned int* ctr, hipStream_t st, FieldArgs f = FieldArgs{}) {
   constexpr int BM = 2 * WM * 32;
   const int64_t T = ceil_div(n, BM);
   const unsigned grid = (unsigned)std::min<int64_t>(T * (T + 1) / 2, device_cu_count());
-  hipLaunchKernelGGL((k_count_mfma<WM, FP4>), dim3(grid), dim3(kThreads), 0, st, bits, n, ld,
-                     (unsigned long long*)hist, ctr);
+  hipLaunchKernelGGL((k_count_mfma<WM, FP4, EPI>), dim3(grid), dim3(kThreads), 0, st, bits, n, ld,
+                     (unsigned long long*)hist, ctr, f);
   CS_LAUNCH_CHECK();
   return CS_OK;
+}
+
+// out[j] = scale (out[j] - phi[j]): the bracket's -phi(j) and the prefactor K / ell^2.
+__global__ void k_field_finish(const double* __restrict__ phi, double* __restrict__ out, int64_t n,
+                               double scale) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) out[j] = __dmul_rn(scale, __dsub_rn(out[j], phi[j]));
 }
 
 cs_status launch_histogram(const uint64_t* bits, int64_t n, int64_t ld, int counter, uint64_t* hist,
@@ -992,6 +1045,39 @@ cs_status launch_histogram(const uint64_t* bits, int64_t n, int64_t ld, int coun
       return CS_OK;
     }
   }
+}
+
+size_t field_ws_bytes(int64_t, int) { return 256; }
+
+cs_status launch_dalembertian(const uint64_t* bits, int64_t n, int64_t ld, int counter, int dim,
+                              double ell, const double* phi, double* out, void* ws, hipStream_t st) {
+  unsigned int* ctr = (unsigned int*)ws;
+  cs_status s = launch_fill_u64((uint64_t*)out, n, 0, st);  // +0.0
+  if (s != CS_OK) return s;
+  s = launch_fill_u64((uint64_t*)ws, 4, 0, st);  // 8 queue counters
+  if (s != CS_OK) return s;
+  // Eqs. b2d_local and b4d_local: K / ell^2 [-phi(j) + sum_m c_m sum_{L_m(j)} phi(i)].
+  FieldArgs f{phi, out, 0.0, 0.0, 0.0, 0.0};
+  double K;
+  if (dim == 2) {
+    K = 2.0;
+    f.c0 = 2.0; f.c1 = -4.0; f.c2 = 2.0;
+  } else {
+    K = 4.0 / sqrt(6.0);
+    f.c0 = 1.0; f.c1 = -9.0; f.c2 = 16.0; f.c3 = -8.0;
+  }
+  const bool big = n > 4096;
+  if (counter == CS_COUNT_MFMA)
+    s = big ? launch_mfma<4, false, 1>(bits, n, ld, nullptr, ctr, st, f)
+            : launch_mfma<2, false, 1>(bits, n, ld, nullptr, ctr, st, f);
+  else
+    s = big ? launch_mfma<4, true, 1>(bits, n, ld, nullptr, ctr, st, f)
+            : launch_mfma<2, true, 1>(bits, n, ld, nullptr, ctr, st, f);
+  if (s != CS_OK) return s;
+  hipLaunchKernelGGL(k_field_finish, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, phi, out, n,
+                     K / (ell * ell));
+  CS_LAUNCH_CHECK();
+  return CS_OK;
 }
 
 cs_status launch_count_batch(int mode, bool fp4, const uint64_t* bits, const BatchInst* inst,

@@ -69,6 +69,17 @@ def test_argument_errors_need_no_device(L):
     assert L.cs_sprinkle(1, 0.0, 1, 1000, p, p, 16, null) == 3
     assert L.cs_interval_histogram(p, 100, 8, 1, p, p, 0, null) == 3
     assert L.cs_interval_histogram(p, 1 << 24, 1 << 18, 2, p, p, 256, null) == 4  # fp4: n < 2^24
+    # d'Alembertian: dimension, counter, scale, pointers, workspace, sizes
+    assert L.cs_dalembertian(p, 100, 8, 3, 1.0, 2, p, p, p, 256, null) == 2
+    assert L.cs_dalembertian(p, 100, 8, 2, 1.0, 0, p, p, p, 256, null) == 2
+    assert L.cs_dalembertian(p, 100, 8, 2, 0.0, 2, p, p, p, 256, null) == 1
+    assert L.cs_dalembertian(p, 100, 8, 2, float("inf"), 2, p, p, p, 256, null) == 1
+    assert L.cs_dalembertian(p, 100, 8, 2, 1.0, 2, null, p, p, 256, null) == 1
+    assert L.cs_dalembertian(p, 100, 8, 2, 1.0, 2, p, p, p, 0, null) == 3
+    assert L.cs_dalembertian(p, 1 << 24, 1 << 18, 4, 1.0, 2, p, p, p, 256, null) == 4
+    assert L.cs_dalembertian(p, 1000, (1 << 19) + 1, 4, 1.0, 1, p, p, p, 256, null) == 4
+    assert L.cs_dalembertian_workspace_bytes(100, 0) == 0
+    assert L.cs_dalembertian_workspace_bytes(100, 2) > 0
     # MFMA counters: 256-row panels must stay below 1 GiB (ld_words <= 2^19)
     assert L.cs_interval_histogram(p, 1000, (1 << 19) + 1, 1, p, p, 256, null) == 4
     assert L.cs_interval_histogram(p, 1000, (1 << 19) + 1, 2, p, p, 256, null) == 4

@@ -23,9 +23,9 @@ _SRC = os.path.join(_HERE, "causal_oracle.c")
 _BUILD = os.path.join(_HERE, "_build")
 _LIB_PATH = os.path.join(_BUILD, "liboracle.so")
 
-MINK2_DIAMOND, MINK4_DIAMOND, DS4_SLAB, DS2_SLAB = 0, 1, 2, 3
-PLANES = {MINK2_DIAMOND: 2, MINK4_DIAMOND: 4, DS4_SLAB: 7, DS2_SLAB: 3}
-DIM = {MINK2_DIAMOND: 2, MINK4_DIAMOND: 4, DS4_SLAB: 4, DS2_SLAB: 2}
+MINK2_DIAMOND, MINK4_DIAMOND, DS4_SLAB, DS2_SLAB, MINK3_DIAMOND = 0, 1, 2, 3, 4
+PLANES = {MINK2_DIAMOND: 2, MINK4_DIAMOND: 4, DS4_SLAB: 7, DS2_SLAB: 3, MINK3_DIAMOND: 3}
+DIM = {MINK2_DIAMOND: 2, MINK4_DIAMOND: 4, DS4_SLAB: 4, DS2_SLAB: 2, MINK3_DIAMOND: 3}
 
 _lib = None
 
@@ -36,7 +36,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
-               "-ffp-contract=off", "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-ffp-contract=off", "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lquadmath", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -69,6 +69,8 @@ def lib():
         L.or_histogram_fast_rows.argtypes = [p, i64, i64, p, p, i64]
         L.or_histogram_fast_rows.restype = i64
         L.or_pair_interval.argtypes = [p, i64, i64, i64]
+        L.or_c3_double.restype = dbl
+        L.or_c3_double.argtypes = []
         L.or_dalembertian.restype = c_int
         L.or_dalembertian.argtypes = [p, i64, i64, c_int, dbl, p, p, p, p]
         L.or_pair_interval.restype = i64

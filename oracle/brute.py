@@ -41,6 +41,9 @@ def smear_exact(dim, m, eps: Fraction) -> Fraction:
     q = one - eps
     if dim == 2:
         br = one - Fraction(2 * m) * eps / q + Fraction(m * (m - 1)) * eps ** 2 / (2 * q ** 2)
+    elif dim == 3:
+        br = (one - Fraction(27 * m) * eps / (8 * q)
+              + Fraction(9 * m * (m - 1)) * eps ** 2 / (8 * q ** 2))
     elif dim == 4:
         br = (one - Fraction(9 * m) * eps / q + Fraction(8 * m * (m - 1)) * eps ** 2 / q ** 2
               - Fraction(4 * m * (m - 1) * (m - 2)) * eps ** 3 / (3 * q ** 3))
@@ -51,17 +54,19 @@ def smear_exact(dim, m, eps: Fraction) -> Fraction:
 
 def smeared_bracket_exact(hist, n, dim, eps: Fraction) -> Fraction:
     """The bracket [N - c eps sum_m N_m f(m, eps)] of the smeared action, exactly
-    (c = 2 in 1+1, c = 1 in 3+1)."""
+    (c = 2 in 1+1, c = 1 in 2+1 and 3+1)."""
     c = 2 if dim == 2 else 1
     s = sum(Fraction(int(h)) * smear_exact(dim, m, eps) for m, h in enumerate(hist) if h)
     return Fraction(n) - c * eps * s
 
 
 def local_integer(hist, n, dim):
-    """The integer combination inside the local BD action."""
+    """The combination inside the local BD action (a rational in 2+1)."""
     h = [int(x) for x in hist] + [0, 0, 0, 0]
     if dim == 2:
         return n - 2 * h[0] + 4 * h[1] - 2 * h[2]
+    if dim == 3:
+        return Fraction(n - h[0]) + Fraction(27, 8) * h[1] - Fraction(9, 4) * h[2]
     return n - h[0] + 9 * h[1] - 16 * h[2] + 8 * h[3]
 
 

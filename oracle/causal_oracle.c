@@ -16,7 +16,8 @@
  *                 (density sec^4(eta) in conformal time, uniform on S^3), and the
  *                 1+1 de Sitter slab of the benchmark section (Sec. 4.3: metric
  *                 sec^2(eta)(-d eta^2 + d theta^2), density sec^2(eta), theta
- *                 uniform on the circle).
+ *                 uniform on the circle), and the 2+1 Minkowski diamond (App. A, here by
+ *                 rejection from the bounding box like the 3+1 one).
  *   time order    Sec. 3.2 "Pairwise Relations": elements are labelled so that a
  *                 later index never precedes an earlier one.
  *   causal matrix Ch. 4 introduction: i and j are related when timelike
@@ -48,9 +49,11 @@
 #include <stdlib.h>
 #include <string.h>
 #include <omp.h>
+#include <quadmath.h>
 
 /* Region codes (same numeric values as the GPU library's public enumeration). */
-enum { OR_MINK2_DIAMOND = 0, OR_MINK4_DIAMOND = 1, OR_DS4_SLAB = 2, OR_DS2_SLAB = 3 };
+enum { OR_MINK2_DIAMOND = 0, OR_MINK4_DIAMOND = 1, OR_DS4_SLAB = 2, OR_DS2_SLAB = 3,
+       OR_MINK3_DIAMOND = 4 };
 
 /* ------------------------------------------------------------------------- */
 /* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014), as in the public-domain       */
@@ -105,6 +108,7 @@ int or_coord_planes(int region)
     case OR_MINK4_DIAMOND: return 4;  /* t, x, y, z                   */
     case OR_DS4_SLAB:      return 7;  /* tan eta, cos eta, sin eta, n0..n3 on S^3 */
     case OR_DS2_SLAB:      return 3;  /* tan eta, eta, theta                        */
+    case OR_MINK3_DIAMOND: return 3;  /* t, x, y                                    */
     default:               return -1;
     }
 }
@@ -176,6 +180,28 @@ int or_sprinkle(int region, double eta0, uint64_t seed, int64_t n, double *coord
                 raw[1 * n + got] = x;
                 raw[2 * n + got] = y;
                 raw[3 * n + got] = z;
+                keys[got].key = kt;
+                keys[got].gen = got;
+                got++;
+            }
+        }
+    } else if (region == OR_MINK3_DIAMOND) {
+        /* 2+1 Alexandrov interval of height 1 between (0,0,0) and (1,0,0): candidates
+         * uniform in [0,1) x [-1/2,1/2)^2, accepted when x^2+y^2 < min(t, 1-t)^2; the
+         * first n accepted, in candidate order, are kept (acceptance pi/12). */
+        uint64_t s = or_stream_key(seed, 5);
+        int64_t got = 0;
+        for (uint64_t c = 0; got < n; c++) {
+            uint64_t kt = or_output(s, 3 * c) >> 11;
+            double t = (double)kt * 0x1.0p-53;
+            double x = or_unit(or_output(s, 3 * c + 1)) - 0.5;
+            double y = or_unit(or_output(s, 3 * c + 2)) - 0.5;
+            double r = t < 1.0 - t ? t : 1.0 - t;
+            double rr = x * x + y * y;
+            if (rr < r * r) {
+                raw[0 * n + got] = t;
+                raw[1 * n + got] = x;
+                raw[2 * n + got] = y;
                 keys[got].key = kt;
                 keys[got].gen = got;
                 got++;
@@ -272,6 +298,12 @@ static int or_related(int region, const double *c, int64_t n, int64_t i, int64_t
         double s = dx * dx + dy * dy;
         s = s + dz * dz;
         return dt * dt > s;
+    } else if (region == OR_MINK3_DIAMOND) {
+        double dt = c[j] - c[i];
+        if (!(dt > 0.0)) return 0;
+        double dx = c[n + j] - c[n + i];
+        double dy = c[2 * n + j] - c[2 * n + i];
+        return dt * dt > dx * dx + dy * dy;
     } else if (region == OR_DS2_SLAB) {
         /* Timelike on the cylinder: the angular separation, measured the short way
          * round, pi - |pi - |theta_i - theta_j||, is below the conformal-time
@@ -504,6 +536,8 @@ static q_t or_smear(int dim, int64_t n, q_t eps)
     int K;
     if (dim == 2) {
         c[0] = 1; c[1] = -2 * nn; c[2] = nn * (nn - 1) / 2; K = 2;
+    } else if (dim == 3) {
+        c[0] = 1; c[1] = -(q_t)27 / 8 * nn; c[2] = (q_t)9 / 8 * nn * (nn - 1); K = 2;
     } else {
         c[0] = 1; c[1] = -9 * nn; c[2] = 8 * nn * (nn - 1);
         c[3] = -(q_t)4 * nn * (nn - 1) * (nn - 2) / 3; K = 3;
@@ -514,20 +548,29 @@ static q_t or_smear(int dim, int64_t n, q_t eps)
     return f;
 }
 
+/* The 2+1 prefactor (1 / Gamma(5/3)) (pi / (3 sqrt 2))^(2/3) (eq. s3d_local, l = l_p). */
+static q_t or_c3(void)
+{
+    q_t p = M_PIq / (3 * sqrtq(2));
+    return cbrtq(p * p) / tgammaq((q_t)5 / 3);
+}
+
 /*
  * Action from the abundances hist[0..n-2] (hist[m] = N_m, pairs with m elements
- * inside).  dim 2 or 4.  eps == 0 selects the local action:
+ * inside).  dim 2, 3 or 4.  eps == 0 selects the local action:
  *   S^(1+1) = 2 (N - 2N_0 + 4N_1 - 2N_2)
+ *   S^(2+1) = C_3 (N - N_0 + (27/8) N_1 - (9/4) N_2)
  *   S^(3+1) = (4/sqrt 6) (N - N_0 + 9N_1 - 16N_2 + 8N_3)        (l = l_p)
- * 0 < eps <= 1 selects the smeared action:
+ * with C_3 = (pi / (3 sqrt 2))^(2/3) / Gamma(5/3).  0 < eps <= 1 selects the smeared action:
  *   S_eps^(1+1) = 2 eps [N - 2 eps sum_m N_m f_2(m, eps)]
+ *   S_eps^(2+1) = C_3 eps^(2/3) [N - eps sum_m N_m f_3(m, eps)]
  *   S_eps^(3+1) = 4 sqrt(eps/6) [N - eps sum_m N_m f_4(m, eps)]
  * Out: *out = S rounded once to double; *kappa = (N + eps_c sum|N_m f_m|)/|bracket|
  * (1 for the local action).  Returns 0, or -1 on bad arguments.
  */
 int or_action(const uint64_t *hist, int64_t n, int dim, double eps, double *out, double *kappa)
 {
-    if (n < 2 || (dim != 2 && dim != 4) || eps < 0.0 || eps > 1.0) return -1;
+    if (n < 2 || (dim != 2 && dim != 3 && dim != 4) || eps < 0.0 || eps > 1.0) return -1;
     int64_t nb = n - 1;
     if (eps == 0.0) {
         int64_t h[4] = {0, 0, 0, 0};
@@ -536,6 +579,9 @@ int or_action(const uint64_t *hist, int64_t n, int dim, double eps, double *out,
         if (dim == 2) {
             int64_t I = n - 2 * h[0] + 4 * h[1] - 2 * h[2];
             s = 2 * (q_t)I;
+        } else if (dim == 3) {
+            int64_t I8 = 8 * n - 8 * h[0] + 27 * h[1] - 18 * h[2];  /* 8 times the bracket */
+            s = or_c3() * (q_t)I8 / 8;
         } else {
             int64_t I = n - h[0] + 9 * h[1] - 16 * h[2] + 8 * h[3];
             s = 4 / q_sqrt(6) * (q_t)I;
@@ -553,7 +599,7 @@ int or_action(const uint64_t *hist, int64_t n, int dim, double eps, double *out,
     }
     q_t ec = dim == 2 ? 2 * e : e;
     q_t bracket = (q_t)n - ec * sum;
-    q_t pref = dim == 2 ? 2 * e : 4 * q_sqrt(e / 6);
+    q_t pref = dim == 2 ? 2 * e : dim == 3 ? or_c3() * cbrtq(e * e) : 4 * q_sqrt(e / 6);
     *out = (double)(pref * bracket);
     if (kappa) {
         q_t ab = bracket < 0 ? -bracket : bracket;
@@ -578,6 +624,7 @@ int or_max_threads(void) { return omp_get_max_threads(); }
  * B phi(j) = (K / ell^2) [ -phi(j) + sum_m c_m sum_{i in L_m(j)} phi(i) ] for every j,
  * with L_m(j) = { i ≺ j : exactly m-1 elements strictly between i and j }:
  *   1+1: K = 2,          c = ( 2, -4,  2)      (the bracket 2 (L1 - 2 L2 + L3))
+ *   2+1: K = C_3,        c = ( 1, -27/8, 9/4)   (eq. b3d_local, C_3 as for the action)
  *   3+1: K = 4/sqrt(6),  c = ( 1, -9, 16, -8)
  * Sums and constants in __float128, one rounding at the end.  Optional outputs for
  * error bounds of other summation orders: terms[j] = 1 + |L_1(j)| + ... (the number
@@ -592,6 +639,8 @@ int or_dalembertian(const uint64_t *bits, int64_t n, int64_t ld, int dim, double
     q_t c[4];
     if (dim == 2) {
         K = 2; layers = 3; c[0] = 2; c[1] = -4; c[2] = 2; c[3] = 0;
+    } else if (dim == 3) {
+        K = or_c3(); layers = 3; c[0] = 1; c[1] = -(q_t)27 / 8; c[2] = (q_t)9 / 4; c[3] = 0;
     } else if (dim == 4) {
         K = 4 / q_sqrt(6); layers = 4; c[0] = 1; c[1] = -9; c[2] = 16; c[3] = -8;
     } else {
@@ -617,3 +666,6 @@ int or_dalembertian(const uint64_t *bits, int64_t n, int64_t ld, int dim, double
     }
     return 0;
 }
+
+/* The 2+1 prefactor rounded to double (for tests). */
+double or_c3_double(void) { return (double)or_c3(); }

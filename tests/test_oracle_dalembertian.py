@@ -1,5 +1,5 @@
 """Pins for the oracle's discrete d'Alembertian B^(d+1) phi (Sec. 4.1, eqs. b2d_local and
-b4d_local), CPU only:
+b3d_local, b4d_local), CPU only:
   * brute force: every labelled 2D order on n <= 5 elements, exact rationals, with the
     order intervals found by enumerating each Alexandroff set;
   * a chain, where L_m(j) = {j - m}, gives the finite-difference stencil of the bracket;
@@ -17,8 +17,9 @@ import pytest
 import workloads as W
 from oracle import brute
 
-K = {2: 2.0, 4: 4.0 / math.sqrt(6.0)}
-C = {2: (2.0, -4.0, 2.0), 4: (1.0, -9.0, 16.0, -8.0)}
+K = {2: 2.0, 3: (math.pi / (3 * math.sqrt(2))) ** (2 / 3) / math.gamma(5 / 3),
+     4: 4.0 / math.sqrt(6.0)}
+C = {2: (2.0, -4.0, 2.0), 3: (1.0, -27 / 8, 9 / 4), 4: (1.0, -9.0, 16.0, -8.0)}
 
 
 def _matrix(orc, region, pts):
@@ -44,13 +45,17 @@ def test_brute_force_all_2d_orders(orc):
             assert [float(w) for w in want] == list(got), (u, v)
 
 
-@pytest.mark.parametrize("dim,region", [(2, W.MINK2_DIAMOND), (4, W.MINK4_DIAMOND)])
+@pytest.mark.parametrize("dim,region", [(2, W.MINK2_DIAMOND), (3, W.MINK3_DIAMOND),
+                                        (4, W.MINK4_DIAMOND)])
 def test_chain_stencil_and_antichain(orc, dim, region):
     n, ell = 12, 0.25
     phi = np.random.default_rng(4).normal(size=n)
     if dim == 2:
         chain = [((k + 1) / 16.0, (k + 1) / 16.0) for k in range(n)]
         anti = [((k + 1) / 16.0, (n - k) / 16.0) for k in range(n)]
+    elif dim == 3:
+        chain = [((k + 1) / 16.0, 0.0, 0.0) for k in range(n)]
+        anti = [(0.5, (k - 6) / 64.0, 0.0) for k in range(n)]
     else:
         chain = [((k + 1) / 16.0, 0.0, 0.0, 0.0) for k in range(n)]
         anti = [(0.5, (k - 6) / 64.0, 0.0, 0.0) for k in range(n)]
@@ -58,15 +63,16 @@ def test_chain_stencil_and_antichain(orc, dim, region):
     got, terms, _ = orc.dalembertian(bits, n, dim, ell, phi)
     for j in range(n):
         br = -phi[j] + sum(c * phi[j - m - 1] for m, c in enumerate(C[dim]) if j - m - 1 >= 0)
-        assert got[j] == pytest.approx(K[dim] / ell ** 2 * br, rel=1e-14, abs=1e-13)
+        assert got[j] == pytest.approx(K[dim] / ell ** 2 * br, rel=1e-13, abs=1e-12)
         assert terms[j] == 1 + min(j, len(C[dim]))
     bits, _ = _matrix(orc, region, anti)
     got, terms, _ = orc.dalembertian(bits, n, dim, ell, phi)
-    assert np.allclose(got, -K[dim] / ell ** 2 * phi, rtol=1e-15, atol=0)
+    assert np.allclose(got, -K[dim] / ell ** 2 * phi, rtol=1e-14, atol=0)
     assert np.all(terms == 1)
 
 
-@pytest.mark.parametrize("dim,region,n", [(2, W.MINK2_DIAMOND, 600), (4, W.MINK4_DIAMOND, 1500)])
+@pytest.mark.parametrize("dim,region,n", [(2, W.MINK2_DIAMOND, 600), (3, W.MINK3_DIAMOND, 1000),
+                                          (4, W.MINK4_DIAMOND, 1500)])
 def test_sum_of_constant_field_is_minus_the_action(orc, dim, region, n):
     ell = 0.3
     c = orc.sprinkle(region, n, seed=5)

@@ -4,7 +4,8 @@ The relation is timelike separation (Ch. 4 introduction), strict on the light
 cone, stored as the symmetric packed matrix P + P^T of Sec. 3.2.  Pinned by:
 partial-order axioms, geometric special cases with exactly representable
 coordinates, and the ordering fractions of the diamonds (1/2 of pairs in 1+1,
-1/10 in 3+1 -- the Myrheim-Meyer fraction Γ(d+1)Γ(d/2)/(2Γ(3d/2)) at d = 2, 4).
+8/35 in 2+1 and 1/10 in 3+1 -- the Myrheim-Meyer fraction Γ(d+1)Γ(d/2)/(2Γ(3d/2)) at
+d = 2, 3, 4).
 """
 import math
 
@@ -19,7 +20,8 @@ def unpack(bits, n):
     return b[:, :n].astype(bool), b[:, n:]
 
 
-@pytest.mark.parametrize("region", [W.MINK2_DIAMOND, W.MINK4_DIAMOND, W.DS4_SLAB])
+@pytest.mark.parametrize("region", [W.MINK2_DIAMOND, W.MINK4_DIAMOND, W.DS4_SLAB,
+                                    W.MINK3_DIAMOND])
 def test_matrix_is_a_partial_order(orc, region):
     n = 700
     c = orc.sprinkle(region, n, seed=21)
@@ -96,6 +98,13 @@ def test_mink2_ordering_fraction_is_half(orc):
     assert abs(m - 0.5) < 5 * se + 1e-3
 
 
+def test_mink3_ordering_fraction(orc):
+    target = math.gamma(4) * math.gamma(1.5) / (2 * math.gamma(4.5))
+    assert abs(target - 8 / 35) < 1e-15
+    m, se = _ordering_fraction(orc, W.MINK3_DIAMOND, 600, range(300, 330))
+    assert abs(m - target) < 4 * se
+
+
 def test_mink4_ordering_fraction_is_tenth(orc):
     g = math.gamma
     target = g(5) * g(2) / (2 * g(6))
@@ -104,7 +113,8 @@ def test_mink4_ordering_fraction_is_tenth(orc):
     assert abs(m - target) < 5 * se + 1e-3
 
 
-@pytest.mark.parametrize("region", [W.MINK2_DIAMOND, W.MINK4_DIAMOND, W.DS4_SLAB])
+@pytest.mark.parametrize("region", [W.MINK2_DIAMOND, W.MINK4_DIAMOND, W.DS4_SLAB,
+                                    W.MINK3_DIAMOND])
 def test_matrix_against_vectorised_predicate(orc, region):
     """Cross-check of the C indexing against a numpy evaluation of the same predicate."""
     n = 333
@@ -118,6 +128,10 @@ def test_matrix_against_vectorised_predicate(orc, region):
         d = [c[k][j] - c[k][i] for k in (1, 2, 3)]
         s = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
         r = (dt > 0) & (dt * dt > s)
+    elif region == W.MINK3_DIAMOND:
+        dt = c[0][j] - c[0][i]
+        dx, dy = c[1][j] - c[1][i], c[2][j] - c[2][i]
+        r = (dt > 0) & (dt * dt > dx * dx + dy * dy)
     else:
         cd = c[1][i] * c[1][j] + c[2][i] * c[2][j]
         dot = ((c[3][i] * c[3][j] + c[4][i] * c[4][j]) + c[5][i] * c[5][j]) + c[6][i] * c[6][j]
@@ -125,7 +139,8 @@ def test_matrix_against_vectorised_predicate(orc, region):
     assert np.array_equal(S[i, j], r)
 
 
-@pytest.mark.parametrize("region", [W.MINK2_DIAMOND, W.MINK4_DIAMOND, W.DS4_SLAB])
+@pytest.mark.parametrize("region", [W.MINK2_DIAMOND, W.MINK4_DIAMOND, W.DS4_SLAB,
+                                    W.MINK3_DIAMOND, W.DS2_SLAB])
 def test_sampled_rows_equal_full_matrix(orc, region):
     n = 1100
     c = orc.sprinkle(region, n, seed=61)

@@ -61,6 +61,21 @@ def test_mink4_support_order_and_marginals(orc):
         assert abs(np.mean(w / r)) < 5 / math.sqrt(3 * n)
 
 
+def test_mink3_support_order_and_marginals(orc):
+    n = 20000
+    t, x, y = orc.sprinkle(W.MINK3_DIAMOND, n, seed=14)
+    r = np.sqrt(x * x + y * y)
+    rmax = np.minimum(t, 1 - t)
+    assert np.all(r < rmax)
+    assert np.all(np.diff(t) >= 0)
+    # 2+1 diamond of height 1: time density ∝ min(t,1-t)^2, CDF 4t^3 / 1 - 4(1-t)^3.
+    cdf = lambda s: np.where(s < 0.5, 4 * s**3, 1 - 4 * (1 - s) ** 3)
+    assert stats.kstest(t, cdf).pvalue > 1e-4
+    # Uniform in each disc: (r/rmax)^2 ~ U(0,1); the angle is uniform.
+    assert stats.kstest((r / rmax) ** 2, "uniform").pvalue > 1e-4
+    assert stats.kstest((np.arctan2(y, x) + math.pi) / (2 * math.pi), "uniform").pvalue > 1e-4
+
+
 def test_ds4_support_order_and_marginals(orc):
     n = 20000
     eta0 = W.DS_ETA0
@@ -87,11 +102,19 @@ def test_ds4_support_order_and_marginals(orc):
 
 
 def test_sprinkle_deterministic(orc):
-    for region in (W.MINK2_DIAMOND, W.MINK4_DIAMOND, W.DS4_SLAB):
+    for region in (W.MINK2_DIAMOND, W.MINK4_DIAMOND, W.DS4_SLAB, W.MINK3_DIAMOND, W.DS2_SLAB):
         a = orc.sprinkle(region, 500, seed=99)
         b = orc.sprinkle(region, 500, seed=99)
         assert np.array_equal(a, b)
         assert not np.array_equal(a, orc.sprinkle(region, 500, seed=100))
+
+
+def test_mink3_prefix_property(orc):
+    a = orc.sprinkle(W.MINK3_DIAMOND, 300, seed=5)
+    b = orc.sprinkle(W.MINK3_DIAMOND, 600, seed=5)
+    # the first 300 accepted candidates are a subset of the first 600
+    sa = set(map(tuple, a.T))
+    assert sa <= set(map(tuple, b.T))
 
 
 def test_mink4_prefix_property(orc):

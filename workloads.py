@@ -19,9 +19,10 @@ MINK2_DIAMOND = 0
 MINK4_DIAMOND = 1
 DS4_SLAB = 2
 DS2_SLAB = 3
+MINK3_DIAMOND = 4
 REGION_NAMES = {MINK2_DIAMOND: "mink2_diamond", MINK4_DIAMOND: "mink4_diamond",
-                DS4_SLAB: "ds4_slab", DS2_SLAB: "ds2_slab"}
-REGION_DIM = {MINK2_DIAMOND: 2, MINK4_DIAMOND: 4, DS4_SLAB: 4, DS2_SLAB: 2}
+                DS4_SLAB: "ds4_slab", DS2_SLAB: "ds2_slab", MINK3_DIAMOND: "mink3_diamond"}
+REGION_DIM = {MINK2_DIAMOND: 2, MINK4_DIAMOND: 4, DS4_SLAB: 4, DS2_SLAB: 2, MINK3_DIAMOND: 3}
 DS_ETA0 = 1.2
 # The 1+1 de Sitter slab of the thesis's action benchmark: eta in [-1/2, 1/2], smearing
 # eps = 2^-6, ten seeds per size, N from 2^10 to 2^17.
@@ -36,6 +37,7 @@ WORKLOADS = {
     "batch_mink2_256": dict(region=MINK2_DIAMOND, count=256, nmin=512, nmax=8192, seed=4,
                             eps=(0.1,)),
     "mink4_n131072": dict(region=MINK4_DIAMOND, n=131072, seed=5, eps=(0.05, 0.1, 0.2)),
+    "mink3_n16384": dict(region=MINK3_DIAMOND, n=16384, seed=6, eps=(0.05, 0.1, 0.2)),
     "ds2_n131072": dict(region=DS2_SLAB, n=131072, seed=DS2_SEEDS[0], eps=(DS2_EPS,),
                         eta0=DS2_ETA0),
 }

@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -52,6 +53,8 @@ def parse():
     ap.add_argument("--no-bitset", action="store_true",
                     help="skip the side legs (the other two counters)")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-field", action="store_true",
+                    help="skip the discrete d'Alembertian leg on the step's matrix")
     ap.add_argument("--no-ds2", action="store_true",
                     help="skip the 1+1 de Sitter action series (the thesis's benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -218,6 +221,29 @@ def main():
     if not args.no_batch and hasattr(L, "cs_batch_run"):
         from bench_batch import run_batch  # noqa: E402  (batch leg lives beside this file)
         out["batch"] = run_batch(cs, torch, dev, stream)
+
+    if not args.no_field:
+        # Discrete d'Alembertian on the step's matrix: the same MFMA tiles with the
+        # per-column epilogue.  phi = 1 makes -ell^2 sum_j B1(j) equal the local action.
+        phi = torch.ones(n, dtype=torch.float64, device=dev)
+        bphi = torch.empty(n, dtype=torch.float64, device=dev)
+        f_ws = torch.empty(max(L.cs_dalembertian_workspace_bytes(n, main), 1), dtype=torch.uint8,
+                           device=dev)
+        ell = 0.01
+        fev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(3)]
+        for k in range(3):
+            fev[k][0].record(stream)
+            cs.cs_dalembertian(bits, n, dim, ell, phi, counter=main, out=bphi, workspace=f_ws,
+                               stream=stream)
+            fev[k][1].record(stream)
+        torch.cuda.synchronize()
+        fms = min(events_ms(fev[1:]))
+        ident = -ell ** 2 * math.fsum(bphi.cpu().numpy())
+        out["dalembertian"] = {"kernel_ms": fms, "frac_peak": 2 * useful_macs / (fms * 1e-3)
+                               / PEAKS[args.counter][0],
+                               "minus_ell2_sum_B1": ident, "local_action": actions[0],
+                               "identity_rel_err": abs(ident - actions[0]) / abs(actions[0])}
 
     if not args.no_ds2:
         from bench_ds2 import run_ds2  # noqa: E402  (lives beside this file)

@@ -65,9 +65,13 @@ typedef enum {
  *                     theta = 2 pi w.  Planes: x = tan(eta), eta, theta.
  *                     i ≺ j iff eta_i < eta_j and pi - |pi - |theta_i - theta_j|| <
  *                     eta_j - eta_i (the angle measured the short way round).
+ *   CS_MINK3_DIAMOND  2+1 Minkowski Alexandrov interval of height 1: uniform by rejection
+ *                     from [0,1) x [-1/2,1/2)^2.  Planes: t, x, y.
+ *                     i ≺ j iff dt > 0 and dt^2 > dx^2 + dy^2.
  * Relations are strict: null-separated and equal-time pairs are unrelated.  All
  * predicates are evaluated in IEEE fp64 in the order written, without contraction. */
-enum { CS_MINK2_DIAMOND = 0, CS_MINK4_DIAMOND = 1, CS_DS4_SLAB = 2, CS_DS2_SLAB = 3 };
+enum { CS_MINK2_DIAMOND = 0, CS_MINK4_DIAMOND = 1, CS_DS4_SLAB = 2, CS_DS2_SLAB = 3,
+       CS_MINK3_DIAMOND = 4 };
 
 /* Interval counters (all three give identical, exact results). */
 enum {
@@ -79,7 +83,7 @@ enum {
                               n < 2^24 (CS_ERR_OVERFLOW otherwise)                        */
 };
 
-/* Number of fp64 coordinate planes of a region (2, 4, 7 or 3); -1 if unknown. */
+/* Number of fp64 coordinate planes of a region (2, 4, 7, 3 or 3); -1 if unknown. */
 int cs_coord_planes(int region);
 
 /* Row stride of the packed matrix in uint64 words: n rounded up to 512 bits. */
@@ -142,7 +146,9 @@ size_t cs_dalembertian_workspace_bytes(int64_t n, int counter);
  *   B phi(j) = (K / ell^2) [ -phi(j) + sum_m c_m sum_{i in L_m(j)} phi(i) ],
  *   L_m(j) = { i ≺ j with exactly m-1 elements strictly between i and j },
  *   dim = 2: K = 2,          (c_1, c_2, c_3)      = (2, -4, 2)
- *   dim = 4: K = 4/sqrt(6),  (c_1, c_2, c_3, c_4) = (1, -9, 16, -8).
+ *   dim = 3: K = C_3,        (c_1, c_2, c_3)      = (1, -27/8, 9/4)      (eq. b3d_local)
+ *   dim = 4: K = 4/sqrt(6),  (c_1, c_2, c_3, c_4) = (1, -9, 16, -8),
+ * with C_3 = (pi / (3 sqrt 2))^(2/3) / Gamma(5/3).
  *   bits     device, the matrix from cs_causal_matrix (n rows, ld_words stride).
  *   ell      discreteness scale (> 0), nu^(-1/(d+1)) for sprinkling density nu.
  *   counter  CS_COUNT_MFMA or CS_COUNT_MFMA_FP4 (the interval sizes come from the same
@@ -162,6 +168,9 @@ cs_status cs_dalembertian(const uint64_t *bits, int64_t n, int64_t ld_words, int
  * Benincasa-Dowker action from the abundances (l = l_p).
  *   dim = 2: eps == 0: S = 2 (N - 2N_0 + 4N_1 - 2N_2)
  *            eps > 0 : S = 2 eps [N - 2 eps sum_m N_m f_2(m, eps)]
+ *   dim = 3: eps == 0: S = C_3 (N - N_0 + (27/8) N_1 - (9/4) N_2)
+ *            eps > 0 : S = C_3 eps^(2/3) [N - eps sum_m N_m f_3(m, eps)]
+ *            with C_3 = (pi / (3 sqrt 2))^(2/3) / Gamma(5/3) (eqs. s3d_local, f_3)
  *   dim = 4: eps == 0: S = (4/sqrt 6)(N - N_0 + 9N_1 - 16N_2 + 8N_3)
  *            eps > 0 : S = 4 sqrt(eps/6) [N - eps sum_m N_m f_4(m, eps)]
  *   0 <= eps <= 1; at eps = 1 the smeared form equals the local one.

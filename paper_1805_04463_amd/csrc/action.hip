@@ -1,11 +1,15 @@
 // Benincasa-Dowker action from the interval abundances (Sec. 4.2).
 //
 // Local:    S^(1+1) = 2 (N - 2N_0 + 4N_1 - 2N_2),
+//           S^(2+1) = C_3 (N - N_0 + (27/8) N_1 - (9/4) N_2),
 //           S^(3+1) = (4/sqrt 6)(N - N_0 + 9N_1 - 16N_2 + 8N_3)      (l = l_p)
 // Smeared:  S_eps^(1+1) = 2 eps [N - 2 eps sum_m N_m f_2(m, eps)]
+//           S_eps^(2+1) = C_3 eps^(2/3) [N - eps sum_m N_m f_3(m, eps)]
 //           S_eps^(3+1) = 4 sqrt(eps/6) [N - eps sum_m N_m f_4(m, eps)]
-// with the smearing functions multiplied out so no power of (1 - eps) is negative:
+// with C_3 = (pi / (3 sqrt 2))^(2/3) / Gamma(5/3) and the smearing functions multiplied
+// out so no power of (1 - eps) is negative:
 //   f_2(m) = (1-e)^(m-2) [(1-e)^2 - 2m e(1-e) + m(m-1)/2 e^2]                m >= 2
+//   f_3(m) = (1-e)^(m-2) [(1-e)^2 - (27/8) m e(1-e) + (9/8) m(m-1) e^2]      m >= 2
 //   f_4(m) = (1-e)^(m-3) [(1-e)^3 - 9m e(1-e)^2 + 8m(m-1) e^2 (1-e)
 //                          - 4 (m(m-1)(m-2)/3) e^3]                          m >= 3
 // and the first terms written directly.  The smeared sum is badly conditioned (the
@@ -78,7 +82,7 @@ __device__ inline dd dd_sqrt(dd a) {  // one Newton step from the fp64 root
   return fast_two_sum(s, corr);
 }
 
-// Bracket polynomials: f(m) = (1-e)^(m-K) * B(m) for m >= K (K = 2 or 4's 3).
+// Bracket polynomials: f(m) = (1-e)^(m-K) * B(m) for m >= K (K = 2, or 3 in 3+1).
 struct Smear {
   int dim;
   dd e, q;              // eps and 1 - eps
@@ -93,6 +97,13 @@ __device__ inline dd bracket(const Smear& s, int64_t m) {
     dd r = s.p[0];
     r = dd_add(r, dd_mul_d(s.p[1], -2.0 * md));
     r = dd_add(r, dd_mul(s.p[2], c2));
+    return r;
+  }
+  if (s.dim == 3) {
+    // (1-e)^2 - (27/8) m e(1-e) + (9/8) m(m-1) e^2 ; 27/8 and 9/8 are exact
+    dd r = s.p[0];
+    r = dd_add(r, dd_mul_d(s.p[1], -3.375 * md));
+    r = dd_add(r, dd_mul(s.p[2], dd_mul_d(two_prod(md, m1), 1.125)));
     return r;
   }
   // (1-e)^3 - 9m e(1-e)^2 + 8m(m-1) e^2(1-e) - 4 (m(m-1)(m-2)/3) e^3
@@ -113,6 +124,9 @@ __device__ inline dd small_weight(const Smear& s, int64_t m) {
   if (s.dim == 2) {  // m = 1: (1-e) - 2e
     return dd_add(s.q, dd_mul_d(s.e, -2.0));
   }
+  if (s.dim == 3) {  // m = 1: (1-e) - (27/8) e
+    return dd_add(s.q, dd_mul_d(s.e, -3.375));
+  }
   if (m == 1) return dd_add(s.q, dd_mul_d(s.e, -9.0));  // (1-e) - 9e
   // m = 2: (1-e)^2 - 18 e(1-e) + 16 e^2
   dd r = dd_mul(s.q, s.q);
@@ -124,8 +138,10 @@ __device__ inline dd small_weight(const Smear& s, int64_t m) {
 constexpr int kActThreads = 1024;
 
 // The action of one histogram by one workgroup of kActThreads threads.
+// c3: for dim 3, the prefactor in double-double (C_3 / 8 for the local action, whose
+// bracket is taken times 8 to stay an integer; C_3 eps^(2/3) for the smeared one).
 __device__ inline void action_block(const uint64_t* __restrict__ hist, int64_t n, int dim, double eps,
-                                    double* __restrict__ out, double* s_hi, double* s_lo) {
+                                    dd c3, double* __restrict__ out, double* s_hi, double* s_lo) {
   const int64_t nb = n - 1;
   if (eps == 0.0) {
     if (threadIdx.x == 0) {
@@ -135,6 +151,12 @@ __device__ inline void action_block(const uint64_t* __restrict__ hist, int64_t n
       if (dim == 2) {
         I = (__int128)n - 2 * h[0] + 4 * h[1] - 2 * h[2];
         out[0] = 2.0 * (double)I;
+      } else if (dim == 3) {
+        I = 8 * (__int128)n - 8 * h[0] + 27 * h[1] - 18 * h[2];
+        double Ihi = (double)I;
+        double Ilo = (double)(I - (__int128)Ihi);
+        dd r = dd_add(dd_mul_d(c3, Ihi), dd_mul_d(c3, Ilo));
+        out[0] = r.hi + r.lo;
       } else {
         I = (__int128)n - h[0] + 9 * h[1] - 16 * h[2] + 8 * h[3];
         // 4/sqrt(6) in double-double times I (I split exactly into two doubles)
@@ -156,7 +178,7 @@ __device__ inline void action_block(const uint64_t* __restrict__ hist, int64_t n
   sm.dim = dim;
   sm.e = {eps, 0.0};
   sm.q = two_sum(1.0, -eps);
-  const int K = dim == 2 ? 2 : 3;
+  const int K = dim == 4 ? 3 : 2;
   for (int k = 0; k <= K; ++k) sm.p[k] = dd_mul(dd_powi(sm.e, k), dd_powi(sm.q, K - k));
 
   const int64_t per = ceil_div(nb, kActThreads);
@@ -195,6 +217,8 @@ __device__ inline void action_block(const uint64_t* __restrict__ hist, int64_t n
     dd pref;
     if (dim == 2) {
       pref = {2.0 * eps, 0.0};
+    } else if (dim == 3) {
+      pref = c3;
     } else {
       // eps/6 in double-double (fp64 quotient plus its exact residual / 6), then sqrt
       double q0 = eps / 6.0;
@@ -208,9 +232,10 @@ __device__ inline void action_block(const uint64_t* __restrict__ hist, int64_t n
 }
 
 __global__ __launch_bounds__(kActThreads) void k_action(const uint64_t* __restrict__ hist, int64_t n,
-                                                        int dim, double eps, double* __restrict__ out) {
+                                                        int dim, double eps, double c3hi, double c3lo,
+                                                        double* __restrict__ out) {
   __shared__ double s_hi[kActThreads], s_lo[kActThreads];
-  action_block(hist, n, dim, eps, out, s_hi, s_lo);
+  action_block(hist, n, dim, eps, dd{c3hi, c3lo}, out, s_hi, s_lo);
 }
 
 // Ensemble: block k * n_eps + e evaluates eps[e] for instance k.
@@ -221,14 +246,27 @@ __global__ __launch_bounds__(kActThreads) void k_action_batch(const uint64_t* __
   __shared__ double s_hi[kActThreads], s_lo[kActThreads];
   const int k = blockIdx.x / n_eps, e = blockIdx.x % n_eps;
   const BatchInst d = inst[k];
-  action_block(hist + d.hist_off, d.n, dim, eps[e], out + blockIdx.x, s_hi, s_lo);
+  action_block(hist + d.hist_off, d.n, dim, eps[e], dd{0.0, 0.0}, out + blockIdx.x, s_hi, s_lo);
 }
 
 }  // namespace
 
+long double prefactor_c3() {  // (pi / (3 sqrt 2))^(2/3) / Gamma(5/3), in extended precision
+  const long double p = acosl(-1.0L) / (3.0L * sqrtl(2.0L));
+  return cbrtl(p * p) / tgammal(5.0L / 3.0L);
+}
+
 cs_status launch_action(const uint64_t* hist, int64_t n, int dim, double eps, double* out,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_action, dim3(1), dim3(kActThreads), 0, st, hist, n, dim, eps, out);
+  double c3hi = 0.0, c3lo = 0.0;
+  if (dim == 3) {
+    const long double c = eps == 0.0 ? prefactor_c3() / 8.0L
+                                     : prefactor_c3() * cbrtl((long double)eps * (long double)eps);
+    c3hi = (double)c;
+    c3lo = (double)(c - (long double)c3hi);
+  }
+  hipLaunchKernelGGL(k_action, dim3(1), dim3(kActThreads), 0, st, hist, n, dim, eps, c3hi, c3lo,
+                     out);
   CS_LAUNCH_CHECK();
   return CS_OK;
 }

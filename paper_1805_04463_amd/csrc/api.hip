@@ -96,7 +96,7 @@ size_t cs_dalembertian_workspace_bytes(int64_t n, int counter) {
 cs_status cs_dalembertian(const uint64_t* bits, int64_t n, int64_t ld_words_, int dim, double ell,
                           int counter, const double* phi, double* out, void* workspace,
                           size_t workspace_bytes, void* stream) {
-  if (dim != 2 && dim != 4) return CS_ERR_UNSUPPORTED;
+  if (dim < 2 || dim > 4) return CS_ERR_UNSUPPORTED;
   if (counter != CS_COUNT_MFMA && counter != CS_COUNT_MFMA_FP4) return CS_ERR_UNSUPPORTED;
   cs_status s = check_n(n);
   if (s != CS_OK) return s;
@@ -111,7 +111,7 @@ cs_status cs_dalembertian(const uint64_t* bits, int64_t n, int64_t ld_words_, in
 
 cs_status cs_action(const uint64_t* hist, int64_t n, int dim, double eps, double* out,
                     void* stream) {
-  if (dim != 2 && dim != 4) return CS_ERR_UNSUPPORTED;
+  if (dim < 2 || dim > 4) return CS_ERR_UNSUPPORTED;
   cs_status s = check_n(n);
   if (s != CS_OK) return s;
   if (!hist || !out || !(eps >= 0.0 && eps <= 1.0)) return CS_ERR_INVALID_ARG;

@@ -36,6 +36,10 @@ template <>
 struct Pt<CS_DS2_SLAB> {
   double eta, th;
 };
+template <>
+struct Pt<CS_MINK3_DIAMOND> {
+  double t, x, y;
+};
 
 __device__ inline Pt<CS_MINK2_DIAMOND> load_pt(const double* c, int64_t n, int64_t i,
                                                Pt<CS_MINK2_DIAMOND>*) {
@@ -53,6 +57,10 @@ __device__ inline Pt<CS_DS4_SLAB> load_pt(const double* c, int64_t n, int64_t i,
 __device__ inline Pt<CS_DS2_SLAB> load_pt(const double* c, int64_t n, int64_t i,
                                           Pt<CS_DS2_SLAB>*) {
   return {c[n + i], c[2 * n + i]};
+}
+__device__ inline Pt<CS_MINK3_DIAMOND> load_pt(const double* c, int64_t n, int64_t i,
+                                               Pt<CS_MINK3_DIAMOND>*) {
+  return {c[i], c[n + i], c[2 * n + i]};
 }
 
 // a ≺ b for a earlier than b in time order.
@@ -75,6 +83,12 @@ __device__ inline bool precedes(const Pt<CS_DS4_SLAB>& a, const Pt<CS_DS4_SLAB>&
   dot = __dadd_rn(dot, __dmul_rn(a.n2, b.n2));
   dot = __dadd_rn(dot, __dmul_rn(a.n3, b.n3));
   return (a.x < b.x) & (cd < dot);
+}
+__device__ inline bool precedes(const Pt<CS_MINK3_DIAMOND>& a, const Pt<CS_MINK3_DIAMOND>& b) {
+  double dt = __dsub_rn(b.t, a.t);
+  double dx = __dsub_rn(b.x, a.x);
+  double dy = __dsub_rn(b.y, a.y);
+  return (dt > 0.0) & (__dmul_rn(dt, dt) > __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)));
 }
 __device__ inline bool precedes(const Pt<CS_DS2_SLAB>& a, const Pt<CS_DS2_SLAB>& b) {
   // The angular separation the short way round, pi - |pi - |theta_a - theta_b||, below
@@ -191,6 +205,7 @@ cs_status launch_causal_matrix(int region, const double* coords, int64_t n, uint
     case CS_MINK4_DIAMOND: return launch_build<CS_MINK4_DIAMOND>(coords, n, bits, ld, st);
     case CS_DS4_SLAB: return launch_build<CS_DS4_SLAB>(coords, n, bits, ld, st);
     case CS_DS2_SLAB: return launch_build<CS_DS2_SLAB>(coords, n, bits, ld, st);
+    case CS_MINK3_DIAMOND: return launch_build<CS_MINK3_DIAMOND>(coords, n, bits, ld, st);
     default: return CS_ERR_UNSUPPORTED;
   }
 }

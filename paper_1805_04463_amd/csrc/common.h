@@ -36,7 +36,8 @@ enum : uint64_t {
   kStreamMink4 = 1,
   kStreamDsTime = 2,
   kStreamDsSphere = 3,
-  kStreamDs2 = 4
+  kStreamDs2 = 4,
+  kStreamMink3 = 5
 };
 
 // Rejection sampling of the S^3 direction gives up after this many tries (probability
@@ -65,6 +66,7 @@ inline int coord_planes(int region) {
     case CS_MINK4_DIAMOND: return 4;
     case CS_DS4_SLAB: return 7;
     case CS_DS2_SLAB: return 3;
+    case CS_MINK3_DIAMOND: return 3;
     default: return -1;
   }
 }
@@ -102,6 +104,7 @@ cs_status launch_causal_matrix(int region, const double* coords, int64_t n, uint
                                int64_t ld, hipStream_t st);
 size_t histogram_ws_bytes(int64_t n, int counter);
 size_t field_ws_bytes(int64_t n, int counter);
+long double prefactor_c3();  // (pi / (3 sqrt 2))^(2/3) / Gamma(5/3), the 2+1 constant
 cs_status launch_dalembertian(const uint64_t* bits, int64_t n, int64_t ld, int counter, int dim,
                               double ell, const double* phi, double* out, void* ws, hipStream_t st);
 cs_status launch_histogram(const uint64_t* bits, int64_t n, int64_t ld, int counter,

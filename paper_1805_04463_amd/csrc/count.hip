@@ -1056,12 +1056,15 @@ cs_status launch_dalembertian(const uint64_t* bits, int64_t n, int64_t ld, int c
   if (s != CS_OK) return s;
   s = launch_fill_u64((uint64_t*)ws, 4, 0, st);  // 8 queue counters
   if (s != CS_OK) return s;
-  // Eqs. b2d_local and b4d_local: K / ell^2 [-phi(j) + sum_m c_m sum_{L_m(j)} phi(i)].
+  // Eqs. b2d_local, b3d_local, b4d_local: K / ell^2 [-phi(j) + sum_m c_m sum_{L_m(j)} phi(i)].
   FieldArgs f{phi, out, 0.0, 0.0, 0.0, 0.0};
   double K;
   if (dim == 2) {
     K = 2.0;
     f.c0 = 2.0; f.c1 = -4.0; f.c2 = 2.0;
+  } else if (dim == 3) {  // eq. b3d_local
+    K = (double)prefactor_c3();
+    f.c0 = 1.0; f.c1 = -3.375; f.c2 = 2.25;
   } else {
     K = 4.0 / sqrt(6.0);
     f.c0 = 1.0; f.c1 = -9.0; f.c2 = 16.0; f.c3 = -8.0;

@@ -15,11 +15,15 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kSortChunk = 2048;  // elements sorted per LDS pass (1024 threads)
 
-// Acceptance budget of the 3+1 rejection sampler: acceptance probability is the
-// diamond's volume pi/24 in the unit box; the budget covers the mean plus 12
-// standard deviations; a one-workgroup tail kernel handles any shortfall.
-int64_t mink4_candidates(int64_t n) {
-  const double p = 0.13089969389957471;  // pi / 24
+// Candidate budget of the rejection samplers of the diamonds of height 1: the
+// acceptance probability is the diamond's volume in the unit box, pi/24 (3+1) or
+// pi/12 (2+1); the budget covers the mean plus 12 standard deviations, and a
+// one-workgroup tail kernel handles any shortfall.
+bool is_rejection(int region) { return region == CS_MINK4_DIAMOND || region == CS_MINK3_DIAMOND; }
+
+int64_t mink_candidates(int region, int64_t n) {
+  const double p = region == CS_MINK3_DIAMOND ? 0.26179938779914941   // pi / 12
+                                              : 0.13089969389957471;  // pi / 24
   double m = (double)n / p + 12.0 * sqrt((double)n * (1.0 - p)) / p + 4096.0;
   return align_up((size_t)m, kBlock);
 }
@@ -34,8 +38,8 @@ struct SprinkleWs {
   double* raw;
   uint64_t* keys;
   uint32_t* gens;
-  uint32_t* blk_count;   // 3+1 only
-  uint64_t* blk_offset;  // 3+1 only (exclusive scan), plus [nblk] = total
+  uint32_t* blk_count;   // rejection samplers only
+  uint64_t* blk_offset;  // rejection samplers only (exclusive scan), plus [nblk] = total
 };
 
 size_t layout(int region, int64_t n, void* base, SprinkleWs* w) {
@@ -51,8 +55,8 @@ size_t layout(int region, int64_t n, void* base, SprinkleWs* w) {
   size_t o_keys = take(sizeof(uint64_t) * P);
   size_t o_gens = take(sizeof(uint32_t) * P);
   size_t o_cnt = 0, o_off = 0;
-  if (region == CS_MINK4_DIAMOND) {
-    int64_t nblk = mink4_candidates(n) / kBlock;
+  if (is_rejection(region)) {
+    int64_t nblk = mink_candidates(region, n) / kBlock;
     o_cnt = take(sizeof(uint32_t) * nblk);
     o_off = take(sizeof(uint64_t) * (nblk + 1));
   }
@@ -61,8 +65,8 @@ size_t layout(int region, int64_t n, void* base, SprinkleWs* w) {
     w->raw = (double*)(b + o_raw);
     w->keys = (uint64_t*)(b + o_keys);
     w->gens = (uint32_t*)(b + o_gens);
-    w->blk_count = region == CS_MINK4_DIAMOND ? (uint32_t*)(b + o_cnt) : nullptr;
-    w->blk_offset = region == CS_MINK4_DIAMOND ? (uint64_t*)(b + o_off) : nullptr;
+    w->blk_count = is_rejection(region) ? (uint32_t*)(b + o_cnt) : nullptr;
+    w->blk_offset = is_rejection(region) ? (uint64_t*)(b + o_off) : nullptr;
   }
   return off;
 }
@@ -88,25 +92,27 @@ __global__ void k_sprinkle_mink2(uint64_t skey, int64_t n, int64_t P, double* __
 }
 
 // ---------------------------------------------------------------------------
-// 3+1 diamond of height 1 by rejection from [0,1) x [-1/2,1/2)^3.
+// D-dimensional diamond of height 1 (D = 3 or 4) by rejection from [0,1) x
+// [-1/2,1/2)^(D-1): candidate c takes draws D c .. D c + D-1 of the stream.
 // ---------------------------------------------------------------------------
-struct Cand4 {
+struct Cand {
   double t, x, y, z;
   uint64_t kt;
   bool ok;
 };
 
-__device__ inline Cand4 mink4_candidate(uint64_t skey, uint64_t c) {
-  Cand4 r;
-  r.kt = sm_output(skey, 4 * c) >> 11;
+template <int D>
+__device__ inline Cand mink_candidate(uint64_t skey, uint64_t c) {
+  Cand r;
+  r.kt = sm_output(skey, D * c) >> 11;
   r.t = (double)r.kt * 0x1.0p-53;
-  r.x = unit53(sm_output(skey, 4 * c + 1)) - 0.5;
-  r.y = unit53(sm_output(skey, 4 * c + 2)) - 0.5;
-  r.z = unit53(sm_output(skey, 4 * c + 3)) - 0.5;
+  r.x = unit53(sm_output(skey, D * c + 1)) - 0.5;
+  r.y = unit53(sm_output(skey, D * c + 2)) - 0.5;
+  r.z = D == 4 ? unit53(sm_output(skey, D * c + 3)) - 0.5 : 0.0;
   double one_t = 1.0 - r.t;
   double rad = r.t < one_t ? r.t : one_t;
   double rr = __dadd_rn(__dmul_rn(r.x, r.x), __dmul_rn(r.y, r.y));
-  rr = __dadd_rn(rr, __dmul_rn(r.z, r.z));
+  if (D == 4) rr = __dadd_rn(rr, __dmul_rn(r.z, r.z));
   r.ok = rr < __dmul_rn(rad, rad);
   return r;
 }
@@ -128,10 +134,11 @@ __device__ inline uint32_t block_rank(bool flag, uint32_t* total, uint32_t* s_wa
   return base + below;
 }
 
-__global__ void k_mink4_count(uint64_t skey, uint32_t* __restrict__ blk_count) {
+template <int D>
+__global__ void k_mink_count(uint64_t skey, uint32_t* __restrict__ blk_count) {
   __shared__ uint32_t s_wave[kBlock / 64];
   uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  Cand4 r = mink4_candidate(skey, c);
+  Cand r = mink_candidate<D>(skey, c);
   uint32_t tot;
   block_rank(r.ok, &tot, s_wave);
   if (threadIdx.x == 0) blk_count[blockIdx.x] = tot;
@@ -160,31 +167,34 @@ __global__ void k_scan_counts(const uint32_t* __restrict__ cnt, int64_t nblk,
   if (threadIdx.x == 0) off[nblk] = carry;
 }
 
-__device__ inline void put4(const Cand4& r, uint64_t rank, int64_t n, double* raw, uint64_t* keys,
+template <int D>
+__device__ inline void put(const Cand& r, uint64_t rank, int64_t n, double* raw, uint64_t* keys,
                             uint32_t* gens) {
   raw[rank] = r.t;
   raw[n + rank] = r.x;
   raw[2 * n + rank] = r.y;
-  raw[3 * n + rank] = r.z;
+  if (D == 4) raw[3 * n + rank] = r.z;
   keys[rank] = r.kt;
   gens[rank] = (uint32_t)rank;
 }
 
-__global__ void k_mink4_scatter(uint64_t skey, int64_t n, const uint64_t* __restrict__ blk_off,
+template <int D>
+__global__ void k_mink_scatter(uint64_t skey, int64_t n, const uint64_t* __restrict__ blk_off,
                                 double* __restrict__ raw, uint64_t* __restrict__ keys,
                                 uint32_t* __restrict__ gens) {
   __shared__ uint32_t s_wave[kBlock / 64];
   uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  Cand4 r = mink4_candidate(skey, c);
+  Cand r = mink_candidate<D>(skey, c);
   uint32_t tot;
   uint32_t local = block_rank(r.ok, &tot, s_wave);
   uint64_t rank = blk_off[blockIdx.x] + local;
-  if (r.ok && rank < (uint64_t)n) put4(r, rank, n, raw, keys, gens);
+  if (r.ok && rank < (uint64_t)n) put<D>(r, rank, n, raw, keys, gens);
 }
 
 // Continues candidates after the budget if (improbably) fewer than n were accepted.
 // One workgroup; bounded number of rounds.
-__global__ void k_mink4_tail(uint64_t skey, int64_t n, int64_t M, const uint64_t* __restrict__ total,
+template <int D>
+__global__ void k_mink_tail(uint64_t skey, int64_t n, int64_t M, const uint64_t* __restrict__ total,
                              double* __restrict__ raw, uint64_t* __restrict__ keys,
                              uint32_t* __restrict__ gens) {
   __shared__ uint32_t s_wave[kBlock / 64];
@@ -192,11 +202,11 @@ __global__ void k_mink4_tail(uint64_t skey, int64_t n, int64_t M, const uint64_t
   const int64_t kMaxRounds = 1ll << 22;
   for (int64_t round = 0; have < (uint64_t)n && round < kMaxRounds; ++round) {
     uint64_t c = (uint64_t)M + (uint64_t)round * kBlock + threadIdx.x;
-    Cand4 r = mink4_candidate(skey, c);
+    Cand r = mink_candidate<D>(skey, c);
     uint32_t tot;
     uint32_t local = block_rank(r.ok, &tot, s_wave);
     uint64_t rank = have + local;
-    if (r.ok && rank < (uint64_t)n) put4(r, rank, n, raw, keys, gens);
+    if (r.ok && rank < (uint64_t)n) put<D>(r, rank, n, raw, keys, gens);
     have += tot;
   }
 }
@@ -427,20 +437,27 @@ cs_status launch_sprinkle(int region, double eta0, uint64_t seed, int64_t n, dou
     hipLaunchKernelGGL(k_sprinkle_mink2, dim3(gridP), dim3(kBlock), 0, st,
                        sm_stream_key(seed, kStreamMink2), n, P, w.raw, w.keys, w.gens);
     CS_LAUNCH_CHECK();
-  } else if (region == CS_MINK4_DIAMOND) {
-    const int64_t M = mink4_candidates(n);
+  } else if (is_rejection(region)) {
+    const bool d4 = region == CS_MINK4_DIAMOND;
+    const int64_t M = mink_candidates(region, n);
     const int64_t nblk = M / kBlock;
-    const uint64_t skey = sm_stream_key(seed, kStreamMink4);
-    hipLaunchKernelGGL(k_mink4_count, dim3((unsigned)nblk), dim3(kBlock), 0, st, skey,
-                       w.blk_count);
+    const uint64_t skey = sm_stream_key(seed, d4 ? kStreamMink4 : kStreamMink3);
+    if (d4) hipLaunchKernelGGL(k_mink_count<4>, dim3((unsigned)nblk), dim3(kBlock), 0, st, skey,
+                               w.blk_count);
+    else hipLaunchKernelGGL(k_mink_count<3>, dim3((unsigned)nblk), dim3(kBlock), 0, st, skey,
+                            w.blk_count);
     CS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, w.blk_count, nblk, w.blk_offset);
     CS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_mink4_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, st, skey, n,
-                       w.blk_offset, w.raw, w.keys, w.gens);
+    if (d4) hipLaunchKernelGGL(k_mink_scatter<4>, dim3((unsigned)nblk), dim3(kBlock), 0, st, skey,
+                               n, w.blk_offset, w.raw, w.keys, w.gens);
+    else hipLaunchKernelGGL(k_mink_scatter<3>, dim3((unsigned)nblk), dim3(kBlock), 0, st, skey,
+                            n, w.blk_offset, w.raw, w.keys, w.gens);
     CS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_mink4_tail, dim3(1), dim3(kBlock), 0, st, skey, n, M,
-                       w.blk_offset + nblk, w.raw, w.keys, w.gens);
+    if (d4) hipLaunchKernelGGL(k_mink_tail<4>, dim3(1), dim3(kBlock), 0, st, skey, n, M,
+                               w.blk_offset + nblk, w.raw, w.keys, w.gens);
+    else hipLaunchKernelGGL(k_mink_tail<3>, dim3(1), dim3(kBlock), 0, st, skey, n, M,
+                            w.blk_offset + nblk, w.raw, w.keys, w.gens);
     CS_LAUNCH_CHECK();
     if (P > n) {
       hipLaunchKernelGGL(k_pad_keys, dim3((unsigned)ceil_div(P - n, kBlock)), dim3(kBlock), 0, st,

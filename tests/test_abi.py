@@ -56,7 +56,7 @@ def test_argument_errors_need_no_device(L):
     # unknown region / counter / dimension
     assert L.cs_sprinkle(5, 1.2, 1, 100, p, p, 1 << 20, null) == 2
     assert L.cs_interval_histogram(p, 100, 8, 3, p, p, 256, null) == 2
-    assert L.cs_action(p, 100, 3, 0.0, p, null) == 2
+    assert L.cs_action(p, 100, 5, 0.0, p, null) == 2
     # n < 2, n >= 2^31
     assert L.cs_causal_matrix(0, p, 1, p, 8, null) == 1
     assert L.cs_causal_matrix(0, p, 1 << 31, p, 1 << 25, null) == 4
@@ -70,7 +70,7 @@ def test_argument_errors_need_no_device(L):
     assert L.cs_interval_histogram(p, 100, 8, 1, p, p, 0, null) == 3
     assert L.cs_interval_histogram(p, 1 << 24, 1 << 18, 2, p, p, 256, null) == 4  # fp4: n < 2^24
     # d'Alembertian: dimension, counter, scale, pointers, workspace, sizes
-    assert L.cs_dalembertian(p, 100, 8, 3, 1.0, 2, p, p, p, 256, null) == 2
+    assert L.cs_dalembertian(p, 100, 8, 5, 1.0, 2, p, p, p, 256, null) == 2
     assert L.cs_dalembertian(p, 100, 8, 2, 1.0, 0, p, p, p, 256, null) == 2
     assert L.cs_dalembertian(p, 100, 8, 2, 0.0, 2, p, p, p, 256, null) == 1
     assert L.cs_dalembertian(p, 100, 8, 2, float("inf"), 2, p, p, p, 256, null) == 1

@@ -159,7 +159,7 @@ def main():
     actions = acts.cpu().tolist()
     peak, kind = PEAKS[args.counter]
     measured_peak = cs.cs_measure_mfma_peak(COUNTERS[args.counter], stream=stream) * 1e12
-    kernel = "k_count_mfma<4, %s>" % ("true" if kind == "fp4" else "false")
+    kernel = "k_count_mfma<4, %s, 0>" % ("true" if kind == "fp4" else "false")
 
     out = {
         "metric": "related-pair interval counts/sec (4D, N=131072), MFMA vs bitset; ensembles/sec",

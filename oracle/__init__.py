@@ -76,6 +76,8 @@ def lib():
         L.or_pair_interval.restype = i64
         L.or_degrees.argtypes = [p, i64, i64, p, p, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         L.or_degrees.restype = c_int
+        L.or_longest_chain.argtypes = [p, i64, i64, p, p, i64, p, p]
+        L.or_longest_chain.restype = c_int
         L.or_action.argtypes = [p, i64, c_int, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
         L.or_action.restype = c_int
         L.or_smear_weight.argtypes = [c_int, i64, dbl]
@@ -180,6 +182,25 @@ def degrees(bits: np.ndarray, n: int):
     lib().or_degrees(_ptr(bits), n, bits.shape[1], _ptr(ind), _ptr(outd),
                      ctypes.byref(c3), ctypes.byref(rel))
     return ind, outd, c3.value, rel.value
+
+
+def longest_chain(bits: np.ndarray, n: int, lo, hi, heights: bool = False):
+    """Alg. "Maximal Chain Length" for pairs (lo[s], hi[s]), -1 <= lo < hi <= n, where -1
+    and n are virtual elements below and above every element.  Returns (length, height):
+    length[s] = links on the longest chain from lo[s] to hi[s] (0 when unrelated);
+    height[s, k] = links on the longest chain from lo[s] to k for k in the Alexandroff
+    set or k = hi[s], else 0 (None unless heights)."""
+    bits = np.ascontiguousarray(bits, dtype=np.uint64)
+    lo = np.ascontiguousarray(np.atleast_1d(lo), dtype=np.int64)
+    hi = np.ascontiguousarray(np.atleast_1d(hi), dtype=np.int64)
+    assert lo.shape == hi.shape
+    length = np.zeros(len(lo), dtype=np.int64)
+    h = np.zeros((len(lo), n), dtype=np.int64) if heights else None
+    rc = lib().or_longest_chain(_ptr(bits), n, bits.shape[1], _ptr(lo), _ptr(hi), len(lo),
+                                _ptr(length), _ptr(h) if heights else None)
+    if rc != 0:
+        raise ValueError("bad longest-chain arguments")
+    return length, h
 
 
 def action(hist: np.ndarray, n: int, dim: int, eps: float = 0.0):

@@ -31,6 +31,11 @@
  *                 forms S_eps with the smearing functions f_2 and f_4.
  *   d'Alembertian Sec. 4.1, eqs. b2d_local and b4d_local: B phi(j) from the sums of
  *                 phi over the inclusive order intervals L_1 .. L_4 of each element.
+ *   chains        Sec. 2.5.2 "Set Partitions", algorithm "Maximal Chain Length": the
+ *                 longest chain between two elements through their Alexandroff set, by
+ *                 the memoised recursion from the future element back to the past one;
+ *                 per-element heights by the same recursion run from the past end.
+ *   degrees       Sec. 3.2 (degree vectors): past and future relations of each element.
  *
  * Parity pins (see tests/test_oracle_*.py): generator test vector, brute-force
  * enumeration of all 2D orders on tiny sets, closed forms (chains, antichains,
@@ -669,3 +674,118 @@ int or_dalembertian(const uint64_t *bits, int64_t n, int64_t ld, int dim, double
 
 /* The 2+1 prefactor rounded to double (for tests). */
 double or_c3_double(void) { return (double)or_c3(); }
+
+/* ------------------------------------------------------------------------- */
+/* Longest chains inside Alexandroff sets (Sec. 2.5.2 "Set Partitions",        */
+/* algorithm "Maximal Chain Length").                                          */
+/*                                                                             */
+/* Indices -1 and n name two virtual elements, one below and one above every  */
+/* element.  A chain's length is its number of links (relations between       */
+/* consecutive elements), which is what the algorithm returns.  Labels are a  */
+/* linear extension of the order, so a ≺ m ≺ b forces a < m < b.              */
+/* ------------------------------------------------------------------------- */
+
+/* Word w of the Alexandroff set A_ab = {m : a ≺ m ≺ b}. */
+static uint64_t or_between_word(const uint64_t *bits, int64_t ld, int64_t n, int64_t a,
+                                int64_t b, int64_t w)
+{
+    const int64_t lo = a + 1 > 0 ? a + 1 : 0, hi = b < n ? b : n; /* indices [lo, hi) */
+    const int64_t base = w << 6;
+    if (base + 64 <= lo || base >= hi) return 0;
+    uint64_t m = ~0ULL;
+    if (lo > base) m &= ~0ULL << (lo - base);
+    if (hi < base + 64) m &= ~0ULL >> (base + 64 - hi);
+    if (a >= 0) m &= bits[a * ld + w]; /* a ≺ m (m later than a and related) */
+    if (b < n) m &= bits[b * ld + w];  /* m ≺ b */
+    return m;
+}
+
+/* Links on the longest chain from k to j: the recursion of the algorithm.  For
+ * every element m of A_kj the distance from m to j is taken from dist[] when known
+ * (-1 marks "not yet"), else computed by the same recursion on A_mj and stored; an
+ * element whose own Alexandroff set with j is empty is one link from j.  The result
+ * is one link more than the largest of those distances (one link when A_kj is empty).
+ * dist[] belongs to this j only. */
+static int64_t or_chain_down(const uint64_t *bits, int64_t ld, int64_t n, int64_t k, int64_t j,
+                             int64_t *dist)
+{
+    int64_t best = 0;
+    const int64_t first = k + 1 > 0 ? k + 1 : 0, last = (j < n ? j : n) - 1;
+    for (int64_t w = first >> 6; first <= last && w <= last >> 6; w++) {
+        uint64_t x = or_between_word(bits, ld, n, k, j, w);
+        while (x) { /* scan the set bits one by one (Alg. "Non-Zero Elements") */
+            const int64_t m = (w << 6) + __builtin_ctzll(x);
+            x &= x - 1;
+            if (dist[m] < 0) dist[m] = or_chain_down(bits, ld, n, m, j, dist);
+            if (dist[m] > best) best = dist[m];
+        }
+    }
+    return best + 1;
+}
+
+/* The same recursion entered from the past end: links on the longest chain from i up to
+ * k, with dist[m] caching the distance from i to m (this i only). */
+static int64_t or_chain_up(const uint64_t *bits, int64_t ld, int64_t n, int64_t i, int64_t k,
+                           int64_t *dist)
+{
+    int64_t best = 0;
+    const int64_t first = i + 1 > 0 ? i + 1 : 0, last = (k < n ? k : n) - 1;
+    for (int64_t w = first >> 6; first <= last && w <= last >> 6; w++) {
+        uint64_t x = or_between_word(bits, ld, n, i, k, w);
+        while (x) {
+            const int64_t m = (w << 6) + __builtin_ctzll(x);
+            x &= x - 1;
+            if (dist[m] < 0) dist[m] = or_chain_up(bits, ld, n, i, m, dist);
+            if (dist[m] > best) best = dist[m];
+        }
+    }
+    return best + 1;
+}
+
+/* a ≺ b, for real or virtual a < b. */
+static int or_precedes(const uint64_t *bits, int64_t ld, int64_t n, int64_t a, int64_t b)
+{
+    if (a < 0 || b >= n) return 1;
+    return or_bit(bits, ld, a, b);
+}
+
+/*
+ * For each pair s, with -1 <= lo[s] < hi[s] <= n:
+ *   length[s]        links on the longest chain from lo[s] to hi[s]; 0 when lo[s] does
+ *                    not precede hi[s];
+ *   height[s*n + k]  (when height is not NULL) links on the longest chain from lo[s] to k,
+ *                    for every k with lo[s] ≺ k and (k ≺ hi[s] or k = hi[s]); 0 elsewhere.
+ * Returns 0, or -1 on bad arguments.
+ */
+int or_longest_chain(const uint64_t *bits, int64_t n, int64_t ld, const int64_t *lo,
+                     const int64_t *hi, int64_t count, int64_t *length, int64_t *height)
+{
+    if (n < 1 || ld * 64 < n || count < 0) return -1;
+    for (int64_t s = 0; s < count; s++)
+        if (lo[s] < -1 || hi[s] > n || lo[s] >= hi[s] || lo[s] >= n || hi[s] < 0) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < count; s++) {
+        const int64_t a = lo[s], b = hi[s];
+        int64_t *dist = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+        const int related = or_precedes(bits, ld, n, a, b);
+        for (int64_t m = 0; m < n; m++) dist[m] = -1;
+        length[s] = related ? or_chain_down(bits, ld, n, a, b, dist) : 0;
+        if (height) {
+            int64_t *h = height + s * n;
+            for (int64_t m = 0; m < n; m++) { h[m] = 0; dist[m] = -1; }
+            if (related) {
+                /* latest first, so that the recursion (not the loop order) fills dist[] */
+                const int64_t top = b < n ? b : n - 1, first = a + 1 > 0 ? a + 1 : 0;
+                for (int64_t k = top; k >= first; k--) {
+                    const int in = or_precedes(bits, ld, n, a, k) &&
+                                   (k == b || or_precedes(bits, ld, n, k, b));
+                    if (!in) continue;
+                    if (dist[k] < 0) dist[k] = or_chain_up(bits, ld, n, a, k, dist);
+                    h[k] = dist[k];
+                }
+            }
+        }
+        free(dist);
+    }
+    return 0;
+}

@@ -12,6 +12,9 @@
  *   cs_interval_histogram  interval abundances N_n (eq. IOIs; algorithms "Naive" and
  *                          "Optimized Interval Abundance Measurement"), two counters
  *   cs_action              Benincasa-Dowker action, local or smeared (Sec. 4.2)
+ *   cs_dalembertian        discrete d'Alembertian of a scalar field (Sec. 4.1)
+ *   cs_longest_chain       longest chains through Alexandroff sets (Sec. 2.5.2), and
+ *   cs_degrees             the degree vectors of the matrix (Sec. 3.2)
  *   cs_batch_*             the four steps for an ensemble of independent 1+1 diamonds in
  *                          one persistent launch per step, capturable in a HIP graph
  *
@@ -163,6 +166,51 @@ size_t cs_dalembertian_workspace_bytes(int64_t n, int counter);
 cs_status cs_dalembertian(const uint64_t *bits, int64_t n, int64_t ld_words, int dim, double ell,
                           int counter, const double *phi, double *out, void *workspace,
                           size_t workspace_bytes, void *stream);
+
+/* Device workspace needed by cs_longest_chain, in bytes (0 for a bad n or count):
+ * about count * (n/4 + 2n) bytes, plus 8n. */
+size_t cs_longest_chain_workspace_bytes(int64_t n, int64_t count);
+
+/*
+ * Longest chains through Alexandroff sets (Sec. 2.5.2 "Set Partitions", algorithm
+ * "Maximal Chain Length"), for `count` pairs at once.  Index -1 names a virtual element
+ * below every element and index n one above every element; a chain's length is its
+ * number of links.  For pair s:
+ *   length[s]          links on the longest chain from lo[s] to hi[s] through
+ *                      A = {k : lo[s] ≺ k ≺ hi[s]}; 0 when lo[s] does not precede hi[s].
+ *                      For (lo, hi) = (-1, n) this is the height of the whole order + 1.
+ *   height[s*n + k]    when height is not NULL: links on the longest chain from lo[s] to k,
+ *                      for k in A or k = hi[s] (when lo[s] ≺ hi[s]); 0 for every other k.
+ *                      With lo[s] = -1 this is one more than the longest distance from a
+ *                      minimal element to k (the antichain partition of the boundary
+ *                      algorithms, Sec. 5.4).
+ *   bits       device, the matrix from cs_causal_matrix (n rows, ld_words stride): labels
+ *              must be a linear extension of the order (i ≺ j implies i < j), as
+ *              cs_sprinkle + cs_causal_matrix produce them.
+ *   lo, hi     HOST arrays of count int64: -1 <= lo[s] < hi[s] <= n, lo[s] < n, hi[s] >= 0
+ *              (CS_ERR_INVALID_ARG otherwise).  1 <= count <= 65535 (CS_ERR_OVERFLOW above).
+ *   length     device, count int32, overwritten.
+ *   height     device, count * n int32, overwritten; or NULL.
+ *   workspace  device, at least cs_longest_chain_workspace_bytes(n, count) bytes.
+ * Unlike the other calls this one returns only after the work is done: it removes the
+ * minimal elements of each set round by round (one round per link of the longest chain)
+ * and reads a progress count back from the device between batches of rounds, which
+ * synchronizes `stream`.  Results are exact integers.
+ */
+cs_status cs_longest_chain(const uint64_t *bits, int64_t n, int64_t ld_words, const int64_t *lo,
+                           const int64_t *hi, int64_t count, int32_t *length, int32_t *height,
+                           void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Degree vectors (Sec. 3.2): for every element k, indeg[k] = number of elements
+ * preceding k and outdeg[k] = number of elements k precedes (with time-ordered labels:
+ * the set bits of row k below and above column k).  Minimal elements have indeg 0,
+ * maximal ones outdeg 0.
+ *   bits    device, the matrix from cs_causal_matrix.
+ *   indeg, outdeg  device, n int64 each, overwritten; either may be NULL, not both.
+ */
+cs_status cs_degrees(const uint64_t *bits, int64_t n, int64_t ld_words, int64_t *indeg,
+                     int64_t *outdeg, void *stream);
 
 /*
  * Benincasa-Dowker action from the abundances (l = l_p).

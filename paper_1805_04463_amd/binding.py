@@ -27,7 +27,8 @@ SYMBOLS = [
     "cs_action", "cs_batch_plan", "cs_batch_workspace_bytes", "cs_batch_hist_len",
     "cs_batch_hist_offset", "cs_batch_run", "cs_batch_free", "cs_batch_graph_create",
     "cs_batch_graph_launch", "cs_batch_graph_destroy", "cs_autotune", "cs_measure_mfma_peak",
-    "cs_dalembertian_workspace_bytes", "cs_dalembertian",
+    "cs_dalembertian_workspace_bytes", "cs_dalembertian", "cs_longest_chain_workspace_bytes",
+    "cs_longest_chain", "cs_degrees",
 ]
 
 
@@ -59,6 +60,9 @@ def lib():
             "cs_action": (c_int, [p, i64, c_int, dbl, p, p]),
             "cs_dalembertian_workspace_bytes": (sz, [i64, c_int]),
             "cs_dalembertian": (c_int, [p, i64, i64, c_int, dbl, c_int, p, p, p, sz, p]),
+            "cs_longest_chain_workspace_bytes": (sz, [i64, i64]),
+            "cs_longest_chain": (c_int, [p, i64, i64, p, p, i64, p, p, p, sz, p]),
+            "cs_degrees": (c_int, [p, i64, i64, p, p, p]),
             "cs_batch_plan": (c_int, [i64, p, c_int, c_int, p, ctypes.c_char_p, ctypes.POINTER(p)]),
             "cs_batch_workspace_bytes": (sz, [p]),
             "cs_batch_hist_len": (i64, [p]),
@@ -170,6 +174,39 @@ def cs_dalembertian(bits: torch.Tensor, n: int, dim: int, ell: float, phi: torch
                                  _ptr(ws), ws.numel(), _stream(stream)), "cs_dalembertian")
     o._cs_keepalive = ws
     return o
+
+
+def cs_longest_chain(bits: torch.Tensor, n: int, lo, hi, heights: bool = False,
+                     workspace: torch.Tensor | None = None, stream=None):
+    """Longest chains (links) from lo[s] to hi[s] for every pair, -1 and n being the
+    virtual elements below and above everything.  Returns (length, height): int32 device
+    tensors of count and (count, n) elements (height None unless requested).  Blocks until
+    done."""
+    import numpy as np
+    lo_h = np.ascontiguousarray(np.atleast_1d(lo), dtype=np.int64)
+    hi_h = np.ascontiguousarray(np.atleast_1d(hi), dtype=np.int64)
+    if lo_h.shape != hi_h.shape:
+        raise CausalError("lo and hi must have the same length")
+    count = len(lo_h)
+    length = torch.empty(count, dtype=torch.int32, device=_dev())
+    height = torch.empty((count, n), dtype=torch.int32, device=_dev()) if heights else None
+    ws_bytes = lib().cs_longest_chain_workspace_bytes(n, count)
+    ws = workspace if workspace is not None else _u8_workspace(max(ws_bytes, 1))
+    _check(lib().cs_longest_chain(_ptr(bits), n, bits.shape[1],
+                                  lo_h.ctypes.data_as(ctypes.c_void_p),
+                                  hi_h.ctypes.data_as(ctypes.c_void_p), count, _ptr(length),
+                                  _ptr(height) if heights else None, _ptr(ws), ws.numel(),
+                                  _stream(stream)), "cs_longest_chain")
+    return length, height
+
+
+def cs_degrees(bits: torch.Tensor, n: int, stream=None):
+    """(indeg, outdeg) of every element as int64 device tensors."""
+    ind = torch.empty(n, dtype=torch.int64, device=_dev())
+    outd = torch.empty(n, dtype=torch.int64, device=_dev())
+    _check(lib().cs_degrees(_ptr(bits), n, bits.shape[1], _ptr(ind), _ptr(outd), _stream(stream)),
+           "cs_degrees")
+    return ind, outd
 
 
 def cs_action(hist: torch.Tensor, n: int, dim: int, eps: float = 0.0,

@@ -13,6 +13,9 @@ constexpr int64_t kMaxN = (int64_t)1 << 31;
 // offsets fit the buffer descriptors' 32-bit range with room for out-of-range requests.
 constexpr int64_t kMaxMfmaLd = (int64_t)1 << 19;
 
+// Longest chains: one grid row per pair.
+constexpr int64_t kMaxChainPairs = 65535;
+
 inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
 cs_status check_n(int64_t n) {
@@ -107,6 +110,35 @@ cs_status cs_dalembertian(const uint64_t* bits, int64_t n, int64_t ld_words_, in
   if (workspace_bytes < field_ws_bytes(n, counter)) return CS_ERR_WORKSPACE;
   return launch_dalembertian(bits, n, ld_words_, counter, dim, ell, phi, out, workspace,
                              as_stream(stream));
+}
+
+size_t cs_longest_chain_workspace_bytes(int64_t n, int64_t count) {
+  if (check_n(n) != CS_OK || count < 1 || count > kMaxChainPairs) return 0;
+  return chain_ws_bytes(n, count);
+}
+
+cs_status cs_longest_chain(const uint64_t* bits, int64_t n, int64_t ld_words_, const int64_t* lo,
+                           const int64_t* hi, int64_t count, int32_t* length, int32_t* height,
+                           void* workspace, size_t workspace_bytes, void* stream) {
+  cs_status s = check_n(n);
+  if (s != CS_OK) return s;
+  if (!bits || !lo || !hi || !length || !workspace || ld_words_ < ld_words(n) || count < 1)
+    return CS_ERR_INVALID_ARG;
+  if (count > kMaxChainPairs) return CS_ERR_OVERFLOW;
+  for (int64_t k = 0; k < count; ++k)
+    if (lo[k] < -1 || lo[k] >= n || hi[k] < 0 || hi[k] > n || lo[k] >= hi[k])
+      return CS_ERR_INVALID_ARG;
+  if (workspace_bytes < chain_ws_bytes(n, count)) return CS_ERR_WORKSPACE;
+  return launch_longest_chain(bits, n, ld_words_, lo, hi, count, length, height, workspace,
+                              as_stream(stream));
+}
+
+cs_status cs_degrees(const uint64_t* bits, int64_t n, int64_t ld_words_, int64_t* indeg,
+                     int64_t* outdeg, void* stream) {
+  cs_status s = check_n(n);
+  if (s != CS_OK) return s;
+  if (!bits || (!indeg && !outdeg) || ld_words_ < ld_words(n)) return CS_ERR_INVALID_ARG;
+  return launch_degrees(bits, n, ld_words_, indeg, outdeg, as_stream(stream));
 }
 
 cs_status cs_action(const uint64_t* hist, int64_t n, int dim, double eps, double* out,

@@ -112,6 +112,13 @@ cs_status launch_histogram(const uint64_t* bits, int64_t n, int64_t ld, int coun
 cs_status launch_action(const uint64_t* hist, int64_t n, int dim, double eps, double* out,
                         hipStream_t st);
 cs_status launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream_t st);
+size_t chain_ws_bytes(int64_t n, int64_t count);
+// Blocks until the rounds are done (reads a per-round progress count back).
+cs_status launch_longest_chain(const uint64_t* bits, int64_t n, int64_t ld, const int64_t* lo,
+                               const int64_t* hi, int64_t count, int32_t* length,
+                               int32_t* height, void* ws, hipStream_t st);
+cs_status launch_degrees(const uint64_t* bits, int64_t n, int64_t ld, int64_t* indeg,
+                         int64_t* outdeg, hipStream_t st);
 int device_cu_count();
 
 // Ensemble pieces (1+1 diamonds).

@@ -80,6 +80,30 @@ def test_argument_errors_need_no_device(L):
     assert L.cs_dalembertian(p, 1000, (1 << 19) + 1, 4, 1.0, 1, p, p, p, 256, null) == 4
     assert L.cs_dalembertian_workspace_bytes(100, 0) == 0
     assert L.cs_dalembertian_workspace_bytes(100, 2) > 0
+    # longest chains: pairs (host arrays), count, pointers, workspace; degrees
+    def pairs(lo, hi):
+        a = (ctypes.c_int64 * len(lo))(*lo)
+        b = (ctypes.c_int64 * len(hi))(*hi)
+        return ctypes.cast(a, ctypes.c_void_p), ctypes.cast(b, ctypes.c_void_p), (a, b)
+    big = 1 << 30
+    for lo, hi in [([5], [5]), ([6], [2]), ([-2], [4]), ([0], [101]), ([100], [101]),
+                   ([-1, 3], [100, 3])]:
+        a, b, keep = pairs(lo, hi)
+        assert L.cs_longest_chain(p, 100, 8, a, b, len(lo), p, null, p, big, null) == 1, (lo, hi)
+    a, b, keep = pairs([-1], [100])
+    assert L.cs_longest_chain(p, 100, 8, a, b, 0, p, null, p, big, null) == 1
+    assert L.cs_longest_chain(p, 100, 8, a, b, 1, null, null, p, big, null) == 1
+    assert L.cs_longest_chain(p, 100, 8, null, b, 1, p, null, p, big, null) == 1
+    assert L.cs_longest_chain(p, 100, 4, a, b, 1, p, null, p, big, null) == 1
+    assert L.cs_longest_chain(p, 1, 8, a, b, 1, p, null, p, big, null) == 1
+    assert L.cs_longest_chain(p, 100, 8, a, b, 1, p, p, p, 16, null) == 3
+    assert L.cs_longest_chain(p, 100, 8, a, b, 65536, p, p, p, big, null) == 4
+    assert L.cs_longest_chain_workspace_bytes(100, 1) > 0
+    assert L.cs_longest_chain_workspace_bytes(100, 0) == 0
+    assert L.cs_longest_chain_workspace_bytes(1, 1) == 0
+    assert L.cs_degrees(p, 100, 8, null, null, null) == 1
+    assert L.cs_degrees(p, 100, 4, p, p, null) == 1
+    assert L.cs_degrees(p, 1, 8, p, p, null) == 1
     # MFMA counters: 256-row panels must stay below 1 GiB (ld_words <= 2^19)
     assert L.cs_interval_histogram(p, 1000, (1 << 19) + 1, 1, p, p, 256, null) == 4
     assert L.cs_interval_histogram(p, 1000, (1 << 19) + 1, 2, p, p, 256, null) == 4

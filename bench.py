@@ -57,6 +57,8 @@ def parse():
                     help="skip the discrete d'Alembertian leg on the step's matrix")
     ap.add_argument("--no-ds2", action="store_true",
                     help="skip the 1+1 de Sitter action series (the thesis's benchmark)")
+    ap.add_argument("--no-chains", action="store_true",
+                    help="skip the longest-chain and degree legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU work for the oracle sample")
@@ -244,6 +246,10 @@ def main():
                                / PEAKS[args.counter][0],
                                "minus_ell2_sum_B1": ident, "local_action": actions[0],
                                "identity_rel_err": abs(ident - actions[0]) / abs(actions[0])}
+
+    if not args.no_chains:
+        from bench_chain import run_chains  # noqa: E402  (lives beside this file)
+        out["chains"] = run_chains(cs, torch, dev, stream, bits, n)
 
     if not args.no_ds2:
         from bench_ds2 import run_ds2  # noqa: E402  (lives beside this file)

@@ -168,7 +168,7 @@ cs_status cs_dalembertian(const uint64_t *bits, int64_t n, int64_t ld_words, int
                           size_t workspace_bytes, void *stream);
 
 /* Device workspace needed by cs_longest_chain, in bytes (0 for a bad n or count):
- * about count * (n/4 + 2n) bytes, plus 8n. */
+ * about 17 * n * count bytes, plus 4n. */
 size_t cs_longest_chain_workspace_bytes(int64_t n, int64_t count);
 
 /*

@@ -1,8 +1,9 @@
 """Ensemble leg of bench.py: 256 independent 1+1 diamonds, N uniform in [512, 8192].
 
 One HIP-graph launch of the batch pipeline (sprinkle, matrix, counts, actions for
-every instance) against the same 256 instances as separate per-instance calls of
-the single-instance entry points.  Both are timed with HIP events on one stream.
+every instance), with each of the three counters, against the same 256 instances as
+separate per-instance calls of the single-instance entry points (int8 counter).  All
+are timed with HIP events on one stream.
 """
 from __future__ import annotations
 
@@ -32,7 +33,8 @@ def run_batch(cs, torch, dev, stream, reps: int = 5):
     out = {"instances": count, "n_range": [int(sizes.min()), int(sizes.max())],
            "tile256_min_n": tuned["tile256_min_n"]}
     results = {}
-    for name, counter in (("mfma", cs.CS_COUNT_MFMA), ("bitset", cs.CS_COUNT_BITSET)):
+    for name, counter in (("mfma", cs.CS_COUNT_MFMA), ("mfma_fp4", cs.CS_COUNT_MFMA_FP4),
+                          ("bitset", cs.CS_COUNT_BITSET)):
         plan = cs.BatchPlan(sizes, counter=counter, eps=eps, tune_cache=tune)
         s = torch.from_numpy(seeds.view(np.int64)).to(dev)
         hist = torch.empty(plan.hist_len, dtype=torch.int64, device=dev)
@@ -100,6 +102,7 @@ def run_batch(cs, torch, dev, stream, reps: int = 5):
     hm, offs = results["mfma"]
     hb, _ = results["bitset"]
     out["mfma_equals_bitset"] = bool(np.array_equal(hm, hb))
+    out["mfma_fp4_equals_bitset"] = bool(np.array_equal(results["mfma_fp4"][0], hb))
     out["per_instance_equals_graph"] = all(
         np.array_equal(last[k], hm[offs[k]:offs[k] + int(sizes[k]) - 1]) for k in last)
     return out

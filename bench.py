@@ -59,6 +59,8 @@ def parse():
                     help="skip the 1+1 de Sitter action series (the thesis's benchmark)")
     ap.add_argument("--no-chains", action="store_true",
                     help="skip the longest-chain and degree legs")
+    ap.add_argument("--no-mink3", action="store_true",
+                    help="skip the 2+1 diamond leg (whole path at the same N, fp4 counter)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU work for the oracle sample")
@@ -250,6 +252,44 @@ def main():
     if not args.no_chains:
         from bench_chain import run_chains  # noqa: E402  (lives beside this file)
         out["chains"] = run_chains(cs, torch, dev, stream, bits, n)
+
+    if not args.no_mink3:
+        # The 2+1 diamond at the same N: the whole path (sprinkle, matrix, fp4 counter, the
+        # local and three smeared S^(2+1)) on the step's buffers, which it overwrites.
+        r3 = W.MINK3_DIAMOND
+        c3 = coords[:cs.cs_coord_planes(r3)]
+        ws3 = torch.empty(L.cs_sprinkle_workspace_bytes(r3, n), dtype=torch.uint8, device=dev)
+        fp4 = COUNTERS["mfma_fp4"]
+        ev3 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(3)]
+        whole = []
+        for k in range(4):
+            torch.cuda.synchronize()
+            tk = time.perf_counter()
+            cs.binding._check(L.cs_sprinkle(r3, eta0, seed, n, cs.binding._ptr(c3),
+                                            cs.binding._ptr(ws3), ws3.numel(),
+                                            cs.binding._stream(stream)), "sprinkle")
+            cs.cs_causal_matrix(r3, c3, n, ld, out=bits, stream=stream)
+            if k:
+                ev3[k - 1][0].record(stream)
+            cs.cs_interval_histogram(bits, n, fp4, out=hist, workspace=hist_ws[fp4], stream=stream)
+            if k:
+                ev3[k - 1][1].record(stream)
+            cs.cs_action(hist, n, 3, 0.0, out=acts[0:1], stream=stream)
+            for j, e in enumerate(eps_list):
+                cs.cs_action(hist, n, 3, e, out=acts[j + 1:j + 2], stream=stream)
+            torch.cuda.synchronize()
+            if k:
+                whole.append((time.perf_counter() - tk) * 1e3)
+        k3 = min(events_ms(ev3))
+        R3 = int(hist.cpu().numpy().view(np.uint64).sum())
+        a3 = acts.cpu().tolist()
+        out["mink3"] = {"n": n, "seed": seed, "relations": R3, "ms_per_step": min(whole),
+                        "counts_per_s": R3 / (min(whole) * 1e-3),
+                        "count_kernel_ms": k3,
+                        "frac_peak": 2 * useful_macs / (k3 * 1e-3) / PEAKS["mfma_fp4"][0],
+                        "actions": {"local": a3[0],
+                                    **{f"eps={e}": a for e, a in zip(eps_list, a3[1:])}}}
 
     if not args.no_ds2:
         from bench_ds2 import run_ds2  # noqa: E402  (lives beside this file)

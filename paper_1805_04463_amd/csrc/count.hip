@@ -585,11 +585,11 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   // Epilogue.  32x32 accumulator layout: lane holds column (lane & 31) and rows
   // 8*(e/4) + 4*(lane/32) + (e%4) for e = 0..15.  Branch-free binning: key = the pair's
   // count if it is related, else 0xFFFFFFFF (unrelated pairs all have count 0).  Every
-  // element issues one LDS add, to its bin when key < HB and otherwise to this lane's own
-  // word past the bins, so misses neither touch a bin nor collide with other lanes.  The
-  // flush range is capped at HB, so tmax may take the spare word's index.  Counts of HB
-  // or more are rare: a second pass over the block, behind a wave-uniform test, adds
-  // them to the global histogram.
+  // element issues one LDS add, to min(key, HB + lane): its bin when key < HB, otherwise
+  // a word past the bins (this lane's own one, or for HB <= key < HB + lane another
+  // lane's), which is never flushed, so misses touch no bin.  tmax, the flush range,
+  // follows the largest related key.  Counts of HB or more are rare: a second pass over
+  // the block, behind a wave-uniform test, adds them to the global histogram.
   const uint32_t spare = (uint32_t)HB + (uint32_t)lane;
 #pragma unroll
   for (int nb = 0; nb < WM; ++nb) {
@@ -597,17 +597,19 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
     for (int mb = 0; mb < WM; ++mb) {
       const uint32_t w = rel[((wave * WM + nb) * WM + mb) * 32 + l32] >> (4 * hsel);
       if (!__ballot(w != 0u)) continue;  // no related pair in this 32x32 block
-      const uint32_t wn = ~w;
+      const int32_t wn = (int32_t)~w;
       uint32_t big = 0;  // max over the block of key + 1 (0 for unrelated pairs)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int sh = (e >> 2) * 8 + (e & 3);
-        const uint32_t key = (uint32_t)acc[mb][nb][e] | (uint32_t)(-(int32_t)((wn >> sh) & 1u));
-        const uint32_t slot = key < (uint32_t)HB ? key : spare;
+        // bit sh of wn, sign-extended: all ones for an unrelated pair, zero for a related one
+        const uint32_t un = (uint32_t)__builtin_amdgcn_sbfe(wn, sh, 1);
+        const uint32_t key = (uint32_t)acc[mb][nb][e] | un;
+        const uint32_t slot = key < spare ? key : spare;
         atomicAdd(lds_hist + slot, 1u);
-        tmax = slot > tmax ? slot : tmax;
         big = key + 1u > big ? key + 1u : big;
       }
+      if (big) tmax = big - 1u > tmax ? big - 1u : tmax;
       if (__ballot(big > (uint32_t)HB)) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {

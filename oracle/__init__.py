@@ -73,6 +73,8 @@ def lib():
         L.or_c3_double.argtypes = []
         L.or_dalembertian.restype = c_int
         L.or_dalembertian.argtypes = [p, i64, i64, c_int, dbl, p, p, p, p]
+        L.or_dalembertian_cols.restype = c_int
+        L.or_dalembertian_cols.argtypes = [p, i64, i64, c_int, dbl, p, p, i64, p, p, p]
         L.or_pair_interval.restype = i64
         L.or_degrees.argtypes = [p, i64, i64, p, p, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         L.or_degrees.restype = c_int
@@ -223,6 +225,20 @@ def dalembertian(bits: np.ndarray, n: int, dim: int, ell: float, phi: np.ndarray
     if lib().or_dalembertian(_ptr(bits), n, bits.shape[1], dim, ell, _ptr(phi), _ptr(out),
                              _ptr(terms), _ptr(mag)) != 0:
         raise ValueError("or_dalembertian failed")
+    return out, terms, mag
+
+
+def dalembertian_cols(bits: np.ndarray, n: int, dim: int, ell: float, phi: np.ndarray, js):
+    """dalembertian() for the elements js only: (out, terms, abs_sum) in the order of js."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    js = np.ascontiguousarray(js, dtype=np.int64)
+    assert phi.shape == (n,)
+    out = np.empty(len(js), dtype=np.float64)
+    terms = np.empty(len(js), dtype=np.int64)
+    mag = np.empty(len(js), dtype=np.float64)
+    if lib().or_dalembertian_cols(_ptr(bits), n, bits.shape[1], dim, ell, _ptr(phi), _ptr(js),
+                                  len(js), _ptr(out), _ptr(terms), _ptr(mag)) != 0:
+        raise ValueError("or_dalembertian_cols failed")
     return out, terms, mag
 
 

@@ -636,8 +636,9 @@ int or_max_threads(void) { return omp_get_max_threads(); }
  * of summands) and abs_sum[j] = |phi(j)| + sum_m |c_m| sum_{i in L_m(j)} |phi(i)|.
  * Returns 0, or -1 on bad arguments.
  */
-int or_dalembertian(const uint64_t *bits, int64_t n, int64_t ld, int dim, double ell,
-                    const double *phi, double *out, int64_t *terms, double *abs_sum)
+static int or_dal_run(const uint64_t *bits, int64_t n, int64_t ld, int dim, double ell,
+                      const double *phi, const int64_t *js, int64_t count, double *out,
+                      int64_t *terms, double *abs_sum)
 {
     q_t K;
     int layers;
@@ -653,8 +654,11 @@ int or_dalembertian(const uint64_t *bits, int64_t n, int64_t ld, int dim, double
     }
     if (n < 1 || ld * 64 < n || !(ell > 0.0)) return -1;
     const q_t scale = K / ((q_t)ell * (q_t)ell);
+    for (int64_t x = 0; x < count; x++)
+        if (js && (js[x] < 0 || js[x] >= n)) return -1;
 #pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t j = 0; j < n; j++) {
+    for (int64_t x = 0; x < count; x++) {
+        const int64_t j = js ? js[x] : x;
         q_t sum = -(q_t)phi[j], mag = fabs(phi[j]);
         int64_t cnt = 1;
         for (int64_t i = 0; i < j; i++) {
@@ -665,11 +669,26 @@ int or_dalembertian(const uint64_t *bits, int64_t n, int64_t ld, int dim, double
             mag += fabs((double)c[m]) * fabs(phi[i]);
             cnt++;
         }
-        out[j] = (double)(scale * sum);
-        if (terms) terms[j] = cnt;
-        if (abs_sum) abs_sum[j] = (double)mag;
+        out[x] = (double)(scale * sum);
+        if (terms) terms[x] = cnt;
+        if (abs_sum) abs_sum[x] = (double)mag;
     }
     return 0;
+}
+
+int or_dalembertian(const uint64_t *bits, int64_t n, int64_t ld, int dim, double ell,
+                    const double *phi, double *out, int64_t *terms, double *abs_sum)
+{
+    return or_dal_run(bits, n, ld, dim, ell, phi, NULL, n, out, terms, abs_sum);
+}
+
+/* The same for the elements js[0 .. count-1] only (outputs in list order). */
+int or_dalembertian_cols(const uint64_t *bits, int64_t n, int64_t ld, int dim, double ell,
+                         const double *phi, const int64_t *js, int64_t count, double *out,
+                         int64_t *terms, double *abs_sum)
+{
+    if (!js || count < 0) return -1;
+    return or_dal_run(bits, n, ld, dim, ell, phi, js, count, out, terms, abs_sum);
 }
 
 /* The 2+1 prefactor rounded to double (for tests). */

@@ -67,3 +67,24 @@ def test_constant_field_gives_the_action(cs, region, dim):
     out = cs.cs_dalembertian(b, n, dim, ell, torch.ones(n, dtype=torch.float64, device="cuda"))
     total = -ell ** 2 * math.fsum(out.cpu().numpy())
     assert total == pytest.approx(s_local, rel=1e-9, abs=1e-6)
+
+
+def test_n131072_sampled_elements(cs, orc):
+    """At the bench size (3+1 diamond, N = 131072, fp4 tiles), B phi of sampled elements
+    against the oracle's sums for those elements, within the summation-order bound."""
+    cfg = W.WORKLOADS["mink4_n131072"]
+    n, seed, ell = cfg["n"], cfg["seed"], 0.01
+    c = cs.cs_sprinkle(W.MINK4_DIAMOND, n, seed)
+    b = cs.cs_causal_matrix(W.MINK4_DIAMOND, c)
+    phi = np.random.default_rng(73).normal(size=n)
+    got = cs.cs_dalembertian(b, n, 4, ell, torch.from_numpy(phi).cuda()).cpu().numpy()
+    torch.cuda.synchronize()
+    bits = b.cpu().numpy().view(np.uint64)
+    del b
+    rng = np.random.default_rng(74)
+    js = np.unique(np.concatenate([[0, 1, n // 2, n - 2, n - 1], rng.integers(0, n, 11)]))
+    want, terms, mag = orc.dalembertian_cols(bits, n, 4, ell, phi, js)
+    bound = K[4] / ell ** 2 * (terms + 2) * 2.0 ** -52 * mag + 8 * 2.0 ** -52 * np.abs(want)
+    err = np.abs(got[js] - want)
+    assert np.all(err <= bound), (js[np.argmax(err / bound)], float(np.max(err / bound)))
+    assert terms.max() > 1

@@ -93,3 +93,17 @@ def test_linearity(orc):
     bab, terms, mab = orc.dalembertian(bits, n, 2, ell, 3 * a + b)
     bound = 4 * (terms + 2) * 2.0 ** -53 * 2 / ell ** 2 * (3 * ma + mb + mab)
     assert np.all(np.abs(bab - (3 * ba + bb)) <= bound)
+
+
+def test_selected_elements_match_the_full_sums(orc):
+    """The per-element entry point (used at sizes where the full sums are too slow) gives
+    the full call's values for the elements it is asked for, in their order."""
+    n = 900
+    c = orc.sprinkle(W.MINK4_DIAMOND, n, 71)
+    bits = orc.causal_matrix(W.MINK4_DIAMOND, c)
+    phi = np.random.default_rng(72).normal(size=n)
+    full = orc.dalembertian(bits, n, 4, 0.05, phi)
+    js = np.array([n - 1, 0, 450, 451, 17, n - 1])
+    part = orc.dalembertian_cols(bits, n, 4, 0.05, phi, js)
+    for a, b in zip(full, part):
+        assert np.array_equal(a[js], b)

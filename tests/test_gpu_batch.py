@@ -67,11 +67,12 @@ def test_batch_tile_shapes(cs, orc, tmp_path, thr, counter):
     check_instances(orc, plan, hist, acts, sizes, seeds, range(len(sizes)))
 
 
-def test_batch_graph_replays(cs, orc):
+@pytest.mark.parametrize("counter", [1, 2], ids=["mfma", "mfma_fp4"])
+def test_batch_graph_replays(cs, orc, counter):
     sizes = [300, 1500, 4200, 6000, 999]
     seeds = [5, 6, 7, 8, 9]
     dev = torch.device("cuda")
-    plan = cs.BatchPlan(sizes, counter=1, eps=EPS)
+    plan = cs.BatchPlan(sizes, counter=counter, eps=EPS)
     s = torch.from_numpy(np.asarray(seeds, dtype=np.uint64).view(np.int64)).to(dev)
     hist = torch.empty(plan.hist_len, dtype=torch.int64, device=dev)
     acts = torch.empty(len(sizes) * len(EPS), dtype=torch.float64, device=dev)
@@ -93,10 +94,11 @@ def test_batch_graph_replays(cs, orc):
                     range(len(sizes)))
 
 
-def test_batch_workload_256(cs, orc):
+@pytest.mark.parametrize("counter", [1, 2], ids=["mfma", "mfma_fp4"])
+def test_batch_workload_256(cs, orc, counter):
     cfg = W.WORKLOADS["batch_mink2_256"]
     sizes, seeds = W.batch_instances(cfg["seed"], cfg["count"], cfg["nmin"], cfg["nmax"])
-    plan, hist, acts = run_batch(cs, sizes, seeds, 1)
+    plan, hist, acts = run_batch(cs, sizes, seeds, counter)
     rng = np.random.default_rng(0)
     which = sorted(set(rng.choice(len(sizes), 6, replace=False).tolist()
                        + [int(np.argmax(sizes)), int(np.argmin(sizes))]))

@@ -243,16 +243,15 @@ __device__ inline void dma_one(__amdgpu_buffer_rsrc_t rsrc, uint32_t lds_stage_a
   const int32_t vo = voff < 0 ? (int32_t)0x80000000 : voff + kbyte;
   const uint32_t lds_addr = lds_stage_addr + wave_off + q * kThreads * 16;
   // Issued as inline assembly so the compiler does not add its own wait for the DMA
-  // before every LDS read; completion is tracked explicitly with wait_vmcnt.  M0 (the
-  // DMA's LDS address) is saved and restored around the load; an LDS DMA needs one wait
-  // state after an SALU write of M0.
-  uint32_t m0_save;
+  // before every LDS read; completion is tracked explicitly with wait_vmcnt.  M0 holds
+  // the DMA's LDS address and is declared clobbered (the compiler keeps nothing there
+  // across the load); an LDS DMA needs one wait state after an SALU write of M0.
   asm volatile(
-      "s_mov_b32 %[sv], m0\n\ts_mov_b32 m0, %[la]\n\ts_nop 0\n\t"
-      "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds\n\ts_mov_b32 m0, %[sv]"
-      : [sv] "=&s"(m0_save)
+      "s_mov_b32 m0, %[la]\n\ts_nop 0\n\t"
+      "buffer_load_dwordx4 %[vo], %[rs], 0 offen lds"
+      :
       : [la] "s"(lds_addr), [vo] "v"(vo), [rs] "s"(rsrc)
-      : "memory");
+      : "memory", "m0");
 }
 
 // A whole stage of a BM-row panel (BM*4/256 requests per thread).

@@ -240,7 +240,10 @@ template <int BM>
 __device__ inline void dma_one(__amdgpu_buffer_rsrc_t rsrc, uint32_t lds_stage_addr, int32_t voff,
                                int32_t kbyte, int q) {
   const uint32_t wave_off = __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) * 64 * 16);
-  const int32_t vo = voff < 0 ? (int32_t)0x80000000 : voff + kbyte;
+  // Rows past n carry an offset of 1 GiB and stages past the last a kbyte of 1 GiB: either
+  // way the request is beyond the descriptor's range (panels are at most 1 GiB) and
+  // reads nothing.  Unsigned, so two such parts add without overflow.
+  const uint32_t vo = (uint32_t)voff + (uint32_t)kbyte;
   const uint32_t lds_addr = lds_stage_addr + wave_off + q * kThreads * 16;
   // Issued as inline assembly so the compiler does not add its own wait for the DMA
   // before every LDS read; completion is tracked explicitly with wait_vmcnt.  M0 holds
@@ -274,7 +277,8 @@ __device__ inline __amdgpu_buffer_rsrc_t uniform_rsrc(const uint32_t* base, uint
                                            (int)nr, 0x00020000);
 }
 
-// Panel byte offsets (row part + chunk) of this thread's DMA slots; -1 marks rows >= n.
+// Panel byte offsets (row part + chunk) of this thread's DMA slots; rows >= n get 1 GiB,
+// past the end of any panel.
 template <int BM>
 __device__ inline void dma_offsets(int32_t* voff_row, int64_t ld, int64_t valid_rows) {
   constexpr int kPer = BM * 4 / kThreads;
@@ -283,7 +287,7 @@ __device__ inline void dma_offsets(int32_t* voff_row, int64_t ld, int64_t valid_
     const int slot = q * kThreads + threadIdx.x;
     const int r = slot >> 2;
     const int c = (slot & 3) ^ ((r >> 2) & 3);
-    voff_row[q] = r < valid_rows ? (int32_t)(r * ld * 8 + c * 16) : -1;
+    voff_row[q] = r < valid_rows ? (int32_t)(r * ld * 8 + c * 16) : (int32_t)0x40000000;
   }
 }
 

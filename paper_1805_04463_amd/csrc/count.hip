@@ -626,30 +626,44 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   }
   } else {
     // d'Alembertian epilogue: per column j of this lane, sum c_m phi(i) over the lane's
-    // related rows i with m interior elements (m < 4; unrelated pairs have key 0xFFFFFFFF);
-    // the two half-waves hold the same columns and are combined by a lane exchange, and
-    // each wave row adds its partial sums to out[j] with one fp64 atomic per column.
+    // related rows i with m interior elements.  c_m comes from a table in LDS after the
+    // rows' phi, indexed by min(key, 4): entry 4 is 0, for m >= 4 and for unrelated pairs
+    // (key 0xFFFFFFFF).  Each row's phi is read once for the WM column blocks.  The two
+    // half-waves hold the same columns and are combined by a lane exchange, and each wave
+    // row adds its partial sums to out[j] with one fp64 atomic per column.
+    const double* ctab = phis + BM;
+    double part[WM];
 #pragma unroll
-    for (int nb = 0; nb < WM; ++nb) {
-      double part = 0.0;
+    for (int nb = 0; nb < WM; ++nb) part[nb] = 0.0;
 #pragma unroll
-      for (int mb = 0; mb < WM; ++mb) {
+    for (int mb = 0; mb < WM; ++mb) {
+      int32_t wn[WM];
+      bool any = false;
+#pragma unroll
+      for (int nb = 0; nb < WM; ++nb) {
         const uint32_t w = rel[((wave * WM + nb) * WM + mb) * 32 + l32] >> (4 * hsel);
-        if (!__ballot(w != 0u)) continue;
-        const uint32_t wn = ~w;
+        any |= w != 0u;
+        wn[nb] = (int32_t)~w;
+      }
+      if (!__ballot(any)) continue;  // no related pair in this row block
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int sh = (e >> 2) * 8 + (e & 3);
-          const uint32_t key = (uint32_t)acc[mb][nb][e] | (uint32_t)(-(int32_t)((wn >> sh) & 1u));
-          const double c = key == 0u ? ta.f.c0 : key == 1u ? ta.f.c1 : key == 2u ? ta.f.c2
-                         : key == 3u ? ta.f.c3 : 0.0;
-          const int r = wr * (WM * 32) + mb * 32 + (e >> 2) * 8 + hsel * 4 + (e & 3);
-          part = __fma_rn(c, phis[r], part);
+      for (int e = 0; e < 16; ++e) {
+        const int sh = (e >> 2) * 8 + (e & 3);
+        const int r = wr * (WM * 32) + mb * 32 + (e >> 2) * 8 + hsel * 4 + (e & 3);
+        const double ph = phis[r];
+#pragma unroll
+        for (int nb = 0; nb < WM; ++nb) {
+          const uint32_t key =
+              (uint32_t)acc[mb][nb][e] | (uint32_t)__builtin_amdgcn_sbfe(wn[nb], sh, 1);
+          part[nb] = __fma_rn(ctab[key < 4u ? key : 4u], ph, part[nb]);
         }
       }
-      part += __shfl_xor(part, 32);
+    }
+#pragma unroll
+    for (int nb = 0; nb < WM; ++nb) {
+      const double sum = part[nb] + __shfl_xor(part[nb], 32);
       const int64_t j = J0 + wc * (WM * 32) + nb * 32 + l32;
-      if (hsel == 0 && part != 0.0 && j < n) atomicAdd(ta.f.out + j, part);
+      if (hsel == 0 && sum != 0.0 && j < n) atomicAdd(ta.f.out + j, sum);
     }
   }
   return true;
@@ -828,7 +842,7 @@ template <int BM, int HB>
 struct MfmaLds {
   uint32_t ring[MRing<BM>::value * 2 * BM * kMStageU32] __attribute__((aligned(16)));
   uint32_t rel[BM * BM / 32];  // relation bits of the current tile's pairs (i < j)
-  double phis[BM];             // phi of the tile's rows (d'Alembertian epilogue)
+  double phis[BM + 8];         // phi of the tile's rows, then c_0 .. c_3, 0 (d'Alembertian)
   uint32_t hist[HB + 64];      // bins, then one spare word per lane (never flushed)
   uint32_t maxbin;
   int slot;
@@ -857,6 +871,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
   const int64_t T = ceil_div(n, BM);
   if constexpr (EPI == 0)
     for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
+  if constexpr (EPI == 1)  // c_m table after the rows' phi (read after the first barrier)
+    if (threadIdx.x < 5)
+      L.phis[BM + threadIdx.x] = threadIdx.x == 0 ? f.c0 : threadIdx.x == 1 ? f.c1
+                                 : threadIdx.x == 2 ? f.c2 : threadIdx.x == 3 ? f.c3 : 0.0;
   uint32_t tmax = 0;
   int64_t pairs_in_lds = 0;
   TileArgs ta{(const uint32_t*)S, 2 * ld, n, 0, 0, hist, f};

@@ -99,6 +99,42 @@ __device__ inline bool precedes(const Pt<CS_DS2_SLAB>& a, const Pt<CS_DS2_SLAB>&
   return (a.eta < b.eta) & (dth < __dsub_rn(b.eta, a.eta));
 }
 
+// a ≺ b for points a, b with b no earlier than a in time order (the builder only
+// asks this).  In the diamonds dt = t_b - t_a >= 0 exactly, and dt * dt > s >= 0 then
+// already excludes dt == 0, so the dt > 0 test of precedes() is dropped: the same answer
+// with one compare fewer.  The other regions ask precedes() as it stands.
+template <int R>
+__device__ inline bool later_precedes(const Pt<R>& a, const Pt<R>& b) {
+  return precedes(a, b);
+}
+template <>
+__device__ inline bool later_precedes(const Pt<CS_MINK4_DIAMOND>& a,
+                                      const Pt<CS_MINK4_DIAMOND>& b) {
+  double dt = __dsub_rn(b.t, a.t);
+  double dx = __dsub_rn(b.x, a.x);
+  double dy = __dsub_rn(b.y, a.y);
+  double dz = __dsub_rn(b.z, a.z);
+  double s = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+  s = __dadd_rn(s, __dmul_rn(dz, dz));
+  return __dmul_rn(dt, dt) > s;
+}
+template <>
+__device__ inline bool later_precedes(const Pt<CS_MINK3_DIAMOND>& a,
+                                      const Pt<CS_MINK3_DIAMOND>& b) {
+  double dt = __dsub_rn(b.t, a.t);
+  double dx = __dsub_rn(b.x, a.x);
+  double dy = __dsub_rn(b.y, a.y);
+  return __dmul_rn(dt, dt) > __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+}
+
+// 2 w + (this lane's bit of the wave mask m): one add with m as the carry-in.
+__device__ inline uint32_t shift_in(uint32_t w, uint64_t m) {
+  uint32_t r;
+  uint64_t carry_out;
+  asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(r), "=s"(carry_out) : "v"(w), "s"(m));
+  return r;
+}
+
 constexpr int kWavesPerBlock = 4;
 
 // 64x64 bit transpose across a wave: lane l holds word x with bit c = element (l, c);
@@ -139,11 +175,15 @@ __device__ inline void build_block(const double* __restrict__ coords, int64_t n,
   cols[lane] = load_pt(coords, n, jv ? j : n - 1, (Pt<R>*)nullptr);
   __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the wave's LDS writes have landed
   __builtin_amdgcn_wave_barrier();
+  // Bit c of the row word is column c: columns enter from the top, 31 first, each
+  // compare's wave mask shifted in as a carry.
   uint32_t lo = 0, hi = 0;
 #pragma unroll
-  for (int c = 0; c < 32; ++c) lo |= (uint32_t)precedes(pi, cols[c]) << c;
+  for (int c = 31; c >= 0; --c)
+    lo = shift_in(lo, __builtin_amdgcn_ballot_w64(later_precedes(pi, cols[c])));
 #pragma unroll
-  for (int c = 0; c < 32; ++c) hi |= (uint32_t)precedes(pi, cols[32 + c]) << c;
+  for (int c = 31; c >= 0; --c)
+    hi = shift_in(hi, __builtin_amdgcn_ballot_w64(later_precedes(pi, cols[32 + c])));
   __builtin_amdgcn_wave_barrier();
   const int64_t ncols = n - bj * 64;  // valid columns of this block (>= 1)
   uint64_t row = ((uint64_t)hi << 32) | lo;
@@ -161,13 +201,41 @@ __device__ inline void build_block(const double* __restrict__ coords, int64_t n,
     for (int64_t w = nb; w < ld; ++w) S[i * ld + w] = 0;
 }
 
+// Patches of 16 x 16 blocks (1024 x 1024 points) of the upper triangle, 64 workgroups
+// each (16 block rows x 4 groups of 4 block columns).  Workgroups are dealt to the 8
+// XCDs in turn, so the workgroups of patch p get ids 8 apart: a patch is built
+// inside one XCD, whose L2 then holds every 128-byte line of its row segments and of
+// its transposed segments until the line is complete, instead of sending partial lines
+// from several L2s to HBM.  Patch p counts row-major over the patches (py, px >= py).
+#ifndef CS_BUILD_PATCH
+#define CS_BUILD_PATCH 16
+#endif
+constexpr int kPatch = CS_BUILD_PATCH;                       // blocks per patch side
+constexpr int kGroups = kPatch / kWavesPerBlock;             // workgroups per patch row
+constexpr int kPatchWgs = kPatch * kGroups;                  // workgroups per patch
+// Grid rows of at most 64 rounds of 8 patches: a row stays far below 2^32 work-items.
+constexpr int64_t kRowWgs = 8 * kPatchWgs * 64;
+
+__device__ inline int64_t patch_row_start(int64_t r, int64_t P) { return r * P - r * (r - 1) / 2; }
+
 template <int R>
 __global__ __launch_bounds__(256) void k_build(const double* __restrict__ coords, int64_t n,
-                                               uint64_t* __restrict__ S, int64_t ld, int64_t nb) {
+                                               uint64_t* __restrict__ S, int64_t ld, int64_t nb,
+                                               int64_t P, int64_t npatch) {
   __shared__ Pt<R> cols[kWavesPerBlock][64];
-  const int64_t bi = blockIdx.y;
-  const int64_t bj = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (bj >= nb || bj < bi) return;  // wave-uniform exit; no block barriers below
+  const int64_t g = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  const int64_t p = (g / (8 * kPatchWgs)) * 8 + (g & 7);
+  if (p >= npatch) return;
+  const int l = (int)((g >> 3) % kPatchWgs);
+  // smaller root of r^2 - (2P+1) r + 2p = 0, then exact correction
+  const double s2 = 2.0 * (double)P + 1.0;
+  int64_t py = (int64_t)((s2 - sqrt(s2 * s2 - 8.0 * (double)p)) * 0.5);
+  while (py > 0 && patch_row_start(py, P) > p) --py;
+  while (patch_row_start(py + 1, P) <= p) ++py;
+  const int64_t px = py + (p - patch_row_start(py, P));
+  const int64_t bi = py * kPatch + l / kGroups;
+  const int64_t bj = (px * kGroups + l % kGroups) * kWavesPerBlock + (threadIdx.x >> 6);
+  if (bi >= nb || bj >= nb || bj < bi) return;  // wave-uniform exit; no block barriers below
   build_block<R>(coords, n, S, ld, nb, bi, bj, cols[threadIdx.x >> 6]);
 }
 
@@ -190,8 +258,12 @@ __global__ __launch_bounds__(256) void k_build_batch(const double* __restrict__ 
 template <int R>
 cs_status launch_build(const double* coords, int64_t n, uint64_t* S, int64_t ld, hipStream_t st) {
   const int64_t nb = ceil_div(n, 64);
-  dim3 grid((unsigned)ceil_div(nb, kWavesPerBlock), (unsigned)nb);
-  hipLaunchKernelGGL(k_build<R>, grid, dim3(64 * kWavesPerBlock), 0, st, coords, n, S, ld, nb);
+  const int64_t P = ceil_div(nb, kPatch), npatch = P * (P + 1) / 2;
+  const int64_t rounds = ceil_div(npatch, 8);  // nb <= 65535: at most 2^20 rounds
+  const dim3 grid((unsigned)(8 * kPatchWgs * std::min<int64_t>(rounds, 64)),
+                  (unsigned)ceil_div(rounds, 64));
+  hipLaunchKernelGGL(k_build<R>, grid, dim3(64 * kWavesPerBlock), 0, st, coords, n, S, ld, nb, P,
+                     npatch);
   CS_LAUNCH_CHECK();
   return CS_OK;
 }

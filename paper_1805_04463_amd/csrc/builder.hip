@@ -4,8 +4,8 @@
 //
 // Work decomposition: one wave per 64x64 block (bi <= bj) of the upper triangle.
 // Lane l owns row i = 64*bi + l (coordinates in registers) and tests it against the
-// 64 column points of block bj, which the wave stages in LDS and reads back as
-// broadcasts; its 64 answers form row i's word for column block bj.  A 64x64 bit
+// 64 column points of block bj, which the wave reads through scalar loads (they are
+// the same for every lane); its 64 answers form row i's word for column block bj.  A 64x64 bit
 // transpose across the wave (six butterfly stages of lane shuffles) turns those row
 // words into the words of rows j for column block bi, so each unordered pair is tested
 // once and both halves of the symmetric matrix are written.
@@ -157,13 +157,50 @@ __device__ inline uint64_t wave_transpose64(uint64_t x) {
   return x;
 }
 
-// One wave: the 64x64 block (bi, bj), bi <= bj, of an n-point matrix S with stride ld.
-// Lane l owns row i = 64 bi + l; the 64 column points are staged in LDS by the wave
-// and read back as broadcasts, and lane l collects its row word bit by bit.  The
-// transposed words (rows of block bj, columns of block bi) come from one 64x64 bit
-// transpose of the row words, so each unordered pair is tested once.  The wave
-// owning the last column block of a row block also zeroes that row block's padding
-// words [nb, ld), so every word of S is written exactly once.
+// Row word of lane l for the 64 column points j0 .. j0+63: bit c is column c.  Columns
+// enter from the top, 63 first, each compare's wave mask shifted in as a carry.  The
+// columns are wave-uniform: they come through scalar loads into SGPRs and feed the fp64
+// operations directly, instead of broadcast reads from LDS (16 bytes per lane per
+// instruction: the LDS bound of the block).  The 7-plane de Sitter slab is the
+// exception: its columns, loaded ahead, do not fit the scalar registers (measured
+// slower), so the wave stages them in LDS.  A block that ends past n repeats point n-1
+// for the missing columns (masked off by the caller).
+template <int R>
+constexpr bool kScalarColumns = R != CS_DS4_SLAB;
+
+template <int R, bool FULL>
+__device__ inline uint64_t row_word(const double* __restrict__ coords, int64_t n, int64_t j0,
+                                    const Pt<R>& pi, Pt<R>* cols) {
+  if constexpr (!kScalarColumns<R>) {
+    const int lane = threadIdx.x & 63;
+    cols[lane] = load_pt(coords, n, j0 + lane < n ? j0 + lane : n - 1, (Pt<R>*)nullptr);
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the wave's LDS writes have landed
+    __builtin_amdgcn_wave_barrier();
+  }
+  uint32_t half[2];
+#pragma unroll
+  for (int h = 1; h >= 0; --h) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int c = 31; c >= 0; --c) {
+      int64_t j = j0 + 32 * h + c;
+      if (!FULL) j = j < n ? j : n - 1;
+      const Pt<R> q = kScalarColumns<R> ? load_pt(coords, n, j, (Pt<R>*)nullptr) : cols[32 * h + c];
+      w = shift_in(w, __builtin_amdgcn_ballot_w64(later_precedes(pi, q)));
+    }
+    half[h] = w;
+  }
+  if constexpr (!kScalarColumns<R>) __builtin_amdgcn_wave_barrier();
+  return ((uint64_t)half[1] << 32) | half[0];
+}
+
+// One wave: the 64x64 block (bi, bj), bi <= bj, of an n-point matrix S with stride ld;
+// bi and bj are wave-uniform.  Lane l owns row i = 64 bi + l and collects its row word
+// for the 64 column points of block bj.  The transposed words (rows of block bj, columns
+// of block bi) come from one 64x64 bit transpose of the row words, so each unordered
+// pair is tested once.  The wave owning the last column block of a row block also
+// zeroes that row block's padding words [nb, ld), so every word of S is written exactly
+// once.
 template <int R>
 __device__ inline void build_block(const double* __restrict__ coords, int64_t n,
                                    uint64_t* __restrict__ S, int64_t ld, int64_t nb, int64_t bi,
@@ -172,21 +209,9 @@ __device__ inline void build_block(const double* __restrict__ coords, int64_t n,
   const int64_t i = bi * 64 + lane, j = bj * 64 + lane;
   const bool iv = i < n, jv = j < n;
   const Pt<R> pi = load_pt(coords, n, iv ? i : n - 1, (Pt<R>*)nullptr);
-  cols[lane] = load_pt(coords, n, jv ? j : n - 1, (Pt<R>*)nullptr);
-  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the wave's LDS writes have landed
-  __builtin_amdgcn_wave_barrier();
-  // Bit c of the row word is column c: columns enter from the top, 31 first, each
-  // compare's wave mask shifted in as a carry.
-  uint32_t lo = 0, hi = 0;
-#pragma unroll
-  for (int c = 31; c >= 0; --c)
-    lo = shift_in(lo, __builtin_amdgcn_ballot_w64(later_precedes(pi, cols[c])));
-#pragma unroll
-  for (int c = 31; c >= 0; --c)
-    hi = shift_in(hi, __builtin_amdgcn_ballot_w64(later_precedes(pi, cols[32 + c])));
-  __builtin_amdgcn_wave_barrier();
+  uint64_t row = bj * 64 + 64 <= n ? row_word<R, true>(coords, n, bj * 64, pi, cols)
+                                   : row_word<R, false>(coords, n, bj * 64, pi, cols);
   const int64_t ncols = n - bj * 64;  // valid columns of this block (>= 1)
-  uint64_t row = ((uint64_t)hi << 32) | lo;
   if (ncols < 64) row &= (1ull << ncols) - 1ull;
   if (bi == bj) row &= lane == 63 ? 0ull : (~0ull << (lane + 1));  // only j > i
   if (!iv) row = 0;
@@ -222,7 +247,7 @@ template <int R>
 __global__ __launch_bounds__(256) void k_build(const double* __restrict__ coords, int64_t n,
                                                uint64_t* __restrict__ S, int64_t ld, int64_t nb,
                                                int64_t P, int64_t npatch) {
-  __shared__ Pt<R> cols[kWavesPerBlock][64];
+  __shared__ Pt<R> cols[kScalarColumns<R> ? 1 : kWavesPerBlock][64];
   const int64_t g = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   const int64_t p = (g / (8 * kPatchWgs)) * 8 + (g & 7);
   if (p >= npatch) return;
@@ -234,9 +259,10 @@ __global__ __launch_bounds__(256) void k_build(const double* __restrict__ coords
   while (patch_row_start(py + 1, P) <= p) ++py;
   const int64_t px = py + (p - patch_row_start(py, P));
   const int64_t bi = py * kPatch + l / kGroups;
-  const int64_t bj = (px * kGroups + l % kGroups) * kWavesPerBlock + (threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t bj = (px * kGroups + l % kGroups) * kWavesPerBlock + wave;
   if (bi >= nb || bj >= nb || bj < bi) return;  // wave-uniform exit; no block barriers below
-  build_block<R>(coords, n, S, ld, nb, bi, bj, cols[threadIdx.x >> 6]);
+  build_block<R>(coords, n, S, ld, nb, bi, bj, cols[kScalarColumns<R> ? 0 : wave]);
 }
 
 // Ensemble of 1+1 diamonds: wave w of block b takes work item 4b + w, packed as
@@ -245,14 +271,13 @@ __global__ __launch_bounds__(256) void k_build_batch(const double* __restrict__ 
                                                      const BatchInst* __restrict__ inst,
                                                      const uint32_t* __restrict__ items,
                                                      int64_t nitems, uint64_t* __restrict__ bits) {
-  __shared__ Pt<CS_MINK2_DIAMOND> cols[kWavesPerBlock][64];
-  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave;
   if (t >= nitems) return;
   const uint32_t it = items[t];
   const BatchInst d = inst[it >> 16];
   build_block<CS_MINK2_DIAMOND>(coords + d.coord_off, d.n, bits + d.bits_off, d.ld,
-                                ceil_div(d.n, 64), (it >> 8) & 255u, it & 255u,
-                                cols[threadIdx.x >> 6]);
+                                ceil_div(d.n, 64), (it >> 8) & 255u, it & 255u, nullptr);
 }
 
 template <int R>

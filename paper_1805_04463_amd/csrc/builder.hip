@@ -159,18 +159,19 @@ __device__ inline uint64_t wave_transpose64(uint64_t x) {
 
 // Row word of lane l for the 64 column points j0 .. j0+63: bit c is column c.  Columns
 // enter from the top, 63 first, each compare's wave mask shifted in as a carry.  The
-// columns are wave-uniform: they come through scalar loads into SGPRs and feed the fp64
-// operations directly, instead of broadcast reads from LDS (16 bytes per lane per
-// instruction: the LDS bound of the block).  The 7-plane de Sitter slab is the
-// exception: its columns, loaded ahead, do not fit the scalar registers (measured
-// slower), so the wave stages them in LDS.  A block that ends past n repeats point n-1
-// for the missing columns (masked off by the caller).
+// columns are wave-uniform.  In the 3+1 and 2+1 diamonds they come through scalar loads
+// into SGPRs and feed the fp64 operations directly, instead of broadcast reads from LDS
+// (16 bytes per lane per instruction: the LDS bound of those blocks).  The other regions
+// stage them in LDS: the 7-plane de Sitter slab's columns, loaded ahead, do not fit the
+// scalar registers, and the two-plane predicates are too short to hide the scalar load
+// latency (both measured slower).  A block that ends past n repeats point n-1 for the
+// missing columns (masked off by the caller).
 template <int R>
-constexpr bool kScalarColumns = R != CS_DS4_SLAB;
+constexpr bool kScalarColumns = R == CS_MINK4_DIAMOND || R == CS_MINK3_DIAMOND;
 
 template <int R, bool FULL>
-__device__ inline uint64_t row_word(const double* __restrict__ coords, int64_t n, int64_t j0,
-                                    const Pt<R>& pi, Pt<R>* cols) {
+__device__ __attribute__((always_inline)) inline uint64_t row_word(
+    const double* __restrict__ coords, int64_t n, int64_t j0, const Pt<R>& pi, Pt<R>* cols) {
   if constexpr (!kScalarColumns<R>) {
     const int lane = threadIdx.x & 63;
     cols[lane] = load_pt(coords, n, j0 + lane < n ? j0 + lane : n - 1, (Pt<R>*)nullptr);
@@ -202,9 +203,9 @@ __device__ inline uint64_t row_word(const double* __restrict__ coords, int64_t n
 // zeroes that row block's padding words [nb, ld), so every word of S is written exactly
 // once.
 template <int R>
-__device__ inline void build_block(const double* __restrict__ coords, int64_t n,
-                                   uint64_t* __restrict__ S, int64_t ld, int64_t nb, int64_t bi,
-                                   int64_t bj, Pt<R>* cols) {
+__device__ __attribute__((always_inline)) inline void build_block(
+    const double* __restrict__ coords, int64_t n, uint64_t* __restrict__ S, int64_t ld, int64_t nb,
+    int64_t bi, int64_t bj, Pt<R>* cols) {
   const int lane = threadIdx.x & 63;
   const int64_t i = bi * 64 + lane, j = bj * 64 + lane;
   const bool iv = i < n, jv = j < n;
@@ -231,7 +232,8 @@ __device__ inline void build_block(const double* __restrict__ coords, int64_t n,
 // XCDs in turn, so the workgroups of patch p get ids 8 apart: a patch is built
 // inside one XCD, whose L2 then holds every 128-byte line of its row segments and of
 // its transposed segments until the line is complete, instead of sending partial lines
-// from several L2s to HBM.  Patch p counts row-major over the patches (py, px >= py).
+// from several L2s to HBM.  Below 8 patches (n <= 3072) they are not dealt: the grid is
+// the patches' own workgroups.  Patch p counts row-major over the patches (py, px >= py).
 #ifndef CS_BUILD_PATCH
 #define CS_BUILD_PATCH 16
 #endif
@@ -249,9 +251,10 @@ __global__ __launch_bounds__(256) void k_build(const double* __restrict__ coords
                                                int64_t P, int64_t npatch) {
   __shared__ Pt<R> cols[kScalarColumns<R> ? 1 : kWavesPerBlock][64];
   const int64_t g = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-  const int64_t p = (g / (8 * kPatchWgs)) * 8 + (g & 7);
+  const bool dealt = npatch >= 8;
+  const int64_t p = dealt ? (g / (8 * kPatchWgs)) * 8 + (g & 7) : g / kPatchWgs;
   if (p >= npatch) return;
-  const int l = (int)((g >> 3) % kPatchWgs);
+  const int l = (int)(dealt ? (g >> 3) % kPatchWgs : g % kPatchWgs);
   // smaller root of r^2 - (2P+1) r + 2p = 0, then exact correction
   const double s2 = 2.0 * (double)P + 1.0;
   int64_t py = (int64_t)((s2 - sqrt(s2 * s2 - 8.0 * (double)p)) * 0.5);
@@ -271,13 +274,14 @@ __global__ __launch_bounds__(256) void k_build_batch(const double* __restrict__ 
                                                      const BatchInst* __restrict__ inst,
                                                      const uint32_t* __restrict__ items,
                                                      int64_t nitems, uint64_t* __restrict__ bits) {
+  __shared__ Pt<CS_MINK2_DIAMOND> cols[kWavesPerBlock][64];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave;
   if (t >= nitems) return;
   const uint32_t it = items[t];
   const BatchInst d = inst[it >> 16];
   build_block<CS_MINK2_DIAMOND>(coords + d.coord_off, d.n, bits + d.bits_off, d.ld,
-                                ceil_div(d.n, 64), (it >> 8) & 255u, it & 255u, nullptr);
+                                ceil_div(d.n, 64), (it >> 8) & 255u, it & 255u, cols[wave]);
 }
 
 template <int R>
@@ -285,8 +289,9 @@ cs_status launch_build(const double* coords, int64_t n, uint64_t* S, int64_t ld,
   const int64_t nb = ceil_div(n, 64);
   const int64_t P = ceil_div(nb, kPatch), npatch = P * (P + 1) / 2;
   const int64_t rounds = ceil_div(npatch, 8);  // nb <= 65535: at most 2^20 rounds
-  const dim3 grid((unsigned)(8 * kPatchWgs * std::min<int64_t>(rounds, 64)),
-                  (unsigned)ceil_div(rounds, 64));
+  const dim3 grid = npatch >= 8 ? dim3((unsigned)(8 * kPatchWgs * std::min<int64_t>(rounds, 64)),
+                                       (unsigned)ceil_div(rounds, 64))
+                                : dim3((unsigned)(kPatchWgs * npatch));
   hipLaunchKernelGGL(k_build<R>, grid, dim3(64 * kWavesPerBlock), 0, st, coords, n, S, ld, nb, P,
                      npatch);
   CS_LAUNCH_CHECK();

@@ -17,8 +17,8 @@
 // double-double (error-free transformations: Knuth's two-sum, Dekker's product via
 // fma), then rounded once.  The local combination is an exact 128-bit integer.
 //
-// One workgroup of 1024 threads; thread t owns a contiguous range of bins and
-// advances (1-e)^(m-3) by one multiplication per bin.
+// One workgroup of 1024 threads per action; bins are dealt in chunks of 8, and the
+// walk stops where the weights have fallen below 1e-304.
 #include "common.h"
 
 namespace cs {
@@ -181,20 +181,29 @@ __device__ inline void action_block(const uint64_t* __restrict__ hist, int64_t n
   const int K = dim == 4 ? 3 : 2;
   for (int k = 0; k <= K; ++k) sm.p[k] = dd_mul(dd_powi(sm.e, k), dd_powi(sm.q, K - k));
 
-  const int64_t per = ceil_div(nb, kActThreads);
-  const int64_t m0 = (int64_t)threadIdx.x * per;
-  const int64_t m1 = (m0 + per < nb ? m0 + per : nb);
+  // Passes of kActThreads chunks of kChunk bins; thread t takes chunk t of each pass and
+  // advances (1-e)^(m-K) by one multiplication per bin.  The weights fall as (1-e)^m:
+  // from the first pass where (1-e)^(m-K) < e^-700 (about 2^-1010) on, a term is at most
+  // 2^-1010 * 2^93 (bracket, m < 2^31) * 2^61 (count), and all of them together stay
+  // below 2^-820, so the passes stop there (near m = 6600 for e = 0.1) instead of
+  // walking all n - 1 bins.
+  constexpr int64_t kChunk = 8;
+  const double log_q = log1p(-eps);  // -inf for eps = 1: only the first pass
   dd acc = {0.0, 0.0};
-  int64_t m = m0;
-  for (; m < m1 && m < K; ++m) {
-    if (hist[m]) acc = dd_add(acc, dd_mul(dd_from_u64(hist[m]), small_weight(sm, m)));
-  }
-  if (m < m1) {
-    dd pw = dd_powi(sm.q, m - K);  // (1-e)^(m-K)
-    for (; m < m1; ++m) {
-      const uint64_t h = hist[m];
-      if (h) acc = dd_add(acc, dd_mul(dd_from_u64(h), dd_mul(pw, bracket(sm, m))));
-      pw = dd_mul(pw, sm.q);
+  for (int64_t base = 0; base < nb; base += kActThreads * kChunk) {
+    if (base > K && (double)(base - K) * log_q < -700.0) break;  // uniform
+    int64_t m = base + (int64_t)threadIdx.x * kChunk;
+    const int64_t m1 = (m + kChunk < nb ? m + kChunk : nb);
+    for (; m < m1 && m < K; ++m) {
+      if (hist[m]) acc = dd_add(acc, dd_mul(dd_from_u64(hist[m]), small_weight(sm, m)));
+    }
+    if (m < m1) {
+      dd pw = dd_powi(sm.q, m - K);  // (1-e)^(m-K)
+      for (; m < m1; ++m) {
+        const uint64_t h = hist[m];
+        if (h) acc = dd_add(acc, dd_mul(dd_from_u64(h), dd_mul(pw, bracket(sm, m))));
+        pw = dd_mul(pw, sm.q);
+      }
     }
   }
   s_hi[threadIdx.x] = acc.hi;

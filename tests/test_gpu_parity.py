@@ -72,6 +72,21 @@ def test_causal_matrix_bit_exact(cs, orc, region, n):
     assert np.array_equal(got, want)
 
 
+ALL_REGIONS = [(W.MINK2_DIAMOND, 1.2), (W.MINK4_DIAMOND, 1.2), (W.DS4_SLAB, W.DS_ETA0),
+               (W.DS2_SLAB, W.DS2_ETA0), (W.MINK3_DIAMOND, 1.2)]
+
+
+@pytest.mark.parametrize("region,eta0", ALL_REGIONS, ids=["mink2", "mink4", "ds4", "ds2", "mink3"])
+@pytest.mark.parametrize("n", [3073, 5000, 9999])
+def test_causal_matrix_patches_bit_exact(cs, orc, region, eta0, n):
+    """Sizes with 8 or more 1024-point patches (dealt over the XCDs) and a ragged last block,
+    in every region (the diamonds' column points come through scalar loads)."""
+    coords = orc.sprinkle(region, n, seed=700 + n, eta0=eta0)
+    want = orc.causal_matrix(region, coords)
+    got = host_u64(cs.cs_causal_matrix(region, torch.from_numpy(coords).cuda()))
+    assert np.array_equal(got, want)
+
+
 def test_causal_matrix_wider_stride(cs, orc):
     n = 300
     coords = orc.sprinkle(W.MINK4_DIAMOND, n, seed=3)

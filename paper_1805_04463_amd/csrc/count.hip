@@ -72,12 +72,19 @@ __device__ inline uint32_t mask_below(int64_t kw, int64_t g) {
   return (1u << (uint32_t)(g - kw)) - 1u;
 }
 
-// The same masks from the offset d = kw - g (fits 32 bits inside a tile).
-__device__ inline uint32_t mask_above_d(int32_t d) {
-  return d > 0 ? 0xFFFFFFFFu : (d <= -31 ? 0u : 0xFFFFFFFFu << (uint32_t)(1 - d));
+// The same masks from the offset d = kw - g, for |d| < 2^30: the shift count is
+// clamped to [0, 32] and the 64-bit shift gives the empty mask at 32.
+__device__ inline uint32_t mask_above_d(int32_t d) {  // bits b with d + b > 0
+  const int32_t s = min(max(1 - d, 0), 32);
+  return (uint32_t)(0xFFFFFFFFull << s);
 }
-__device__ inline uint32_t mask_below_d(int32_t d) {
-  return d <= -32 ? 0xFFFFFFFFu : (d >= 0 ? 0u : (1u << (uint32_t)(-d)) - 1u);
+__device__ inline uint32_t mask_below_d(int32_t d) {  // bits b with d + b < 0
+  const int32_t s = min(max(-d, 0), 32);
+  return ~(uint32_t)(0xFFFFFFFFull << s);
+}
+// A tile-relative offset as int32: outside +-2^24 every mask is all-or-nothing anyway.
+__device__ inline int32_t clamp_offset(int64_t v) {
+  return (int32_t)(v < -(1 << 24) ? -(1 << 24) : (v > (1 << 24) ? (1 << 24) : v));
 }
 
 // LDS position (in uint32) of the 16-byte half `h` of staged row r: rows are 8
@@ -325,22 +332,27 @@ constexpr int fp4_class_scale() { return C == 1 ? 127 : C == 2 ? 126 : 128; }
 // diagonal block of the tile: A rows (i = I0 + r) keep k > i, B rows (j = J0 + r) keep
 // k < j, for the stage's bits k in [kb, kb + 512).  The masks depend only on the row and
 // k, so one pass serves every wave that reads the row.
+// A side only when the stage starts at or before the last A row, B side only when it
+// ends past the first B row; rows are dealt so that each wave takes one side.
 template <int BM>
 __device__ inline void mask_stage(uint32_t* As, uint32_t* Bs, int64_t kb, int64_t I0, int64_t J0) {
+  static_assert(BM % 64 == 0, "a wave's rows lie on one side");
+  const bool need_a = kb <= I0 + BM - 1, need_b = kb + kMStageBits > J0;
+  const int32_t da = clamp_offset(kb - I0), db = clamp_offset(kb - J0);
   for (int x = threadIdx.x; x < 2 * BM; x += kThreads) {
-    const bool is_a = x < BM;
+    const bool is_a = __builtin_amdgcn_readfirstlane(x) < BM;  // the same for the whole wave
+    if (!(is_a ? need_a : need_b)) continue;
     const int r = is_a ? x : x - BM;
     uint32_t* P = is_a ? As : Bs;
-    const int64_t g = (is_a ? I0 : J0) + r;
+    const int32_t d0 = (is_a ? da : db) - r;  // first bit of the stage minus the row index
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       uint4 v = *(uint4*)(P + mpos(r, c));
       uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        int64_t d = kb + 128 * c + 32 * q - g;  // word start minus the row index
-        d = d < -64 ? -64 : (d > 64 ? 64 : d);
-        w[q] &= is_a ? mask_above_d((int32_t)d) : mask_below_d((int32_t)d);
+        const int32_t d = d0 + 128 * c + 32 * q;  // word start minus the row index
+        w[q] &= is_a ? mask_above_d(d) : mask_below_d(d);
       }
       *(uint4*)(P + mpos(r, c)) = make_uint4(w[0], w[1], w[2], w[3]);
     }
@@ -456,7 +468,9 @@ __device__ inline void mfma_stage(Acc (&acc)[WM][WM], uint4 (&aw)[2][WM], uint4 
 
 // EPI 0: histogram of the interval sizes of the related pairs.  EPI 1: d'Alembertian
 // sums, per column j, of c_m phi(i) over the related pairs (i, j) with m interior elements.
-template <int WM, int HB, bool FP4 = false, int EPI = 0>
+// FITS: every count is below HB (instances of at most HB + 1 points), so the epilogue
+// neither tracks the largest bin (the caller flushes all n - 1) nor needs its second pass.
+template <int WM, int HB, bool FP4 = false, int EPI = 0, bool FITS = false>
 __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& ta, uint32_t* ring,
                                                                 uint32_t* rel, uint32_t* lds_hist,
                                                                 uint32_t& tmax, double* phis) {
@@ -511,12 +525,13 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
     __syncthreads();
     bool any = false;
     const uint32_t* Bs0 = ring + kStage;
+    const int32_t dij = clamp_offset(I0 - J0);
 #pragma unroll
     for (int nb = 0; nb < WM; ++nb)
 #pragma unroll
       for (int mb = 0; mb < WM; ++mb) {
         const int br = wc * (WM * 32) + nb * 32 + l32, m = wr * WM + mb;
-        const uint32_t w = Bs0[mpos(br, m >> 2) + (m & 3)] & mask_below(I0 + 32 * m, J0 + br);
+        const uint32_t w = Bs0[mpos(br, m >> 2) + (m & 3)] & mask_below_d(dij + 32 * m - br);
         any |= w != 0u;
         if (hsel == 0) rel[((wave * WM + nb) * WM + mb) * 32 + l32] = w;
       }
@@ -610,8 +625,9 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
         const uint32_t key = (uint32_t)acc[mb][nb][e] | un;
         const uint32_t slot = key < spare ? key : spare;
         atomicAdd(lds_hist + slot, 1u);
-        big = key + 1u > big ? key + 1u : big;
+        if constexpr (!FITS) big = key + 1u > big ? key + 1u : big;
       }
+      if constexpr (FITS) continue;
       if (big) tmax = big - 1u > tmax ? big - 1u : tmax;
       if (__ballot(big > (uint32_t)HB)) {
 #pragma unroll
@@ -957,6 +973,8 @@ struct BatchLdsOf<0> {
   using type = BitsetLds<kBinsBatch>;
 };
 
+static_assert(kBinsBatch >= kBatchMaxN - 1, "ensemble counts fit the LDS bins");
+
 template <int MODE, bool FP4 = false>
 __global__ __launch_bounds__(kThreads, MODE == 4 ? 1 : 2) void k_count_batch(
     const uint64_t* __restrict__ bits, const BatchInst* __restrict__ inst,
@@ -981,6 +999,7 @@ __global__ __launch_bounds__(kThreads, MODE == 4 ? 1 : 2) void k_count_batch(
       ta.ld32 = 2 * d.ld;
       ta.n = d.n;
       ta.hist = hist + d.hist_off;
+      if constexpr (MODE != 0) tmax = (uint32_t)(d.n - 2);  // FITS: flush every bin
     }
     const int64_t I = (int64_t)((it >> 8) & 255u);
     const int64_t T = ceil_div(ta.n, BM);
@@ -990,7 +1009,7 @@ __global__ __launch_bounds__(kThreads, MODE == 4 ? 1 : 2) void k_count_batch(
       if constexpr (MODE == 0)
         bitset_tile<HB>(ta, L.As, L.Bs, L.hist, tmax);
       else
-        mfma_tile<MODE, HB, FP4>(ta, L.ring, L.rel, L.hist, tmax, nullptr);
+        mfma_tile<MODE, HB, FP4, 0, true>(ta, L.ring, L.rel, L.hist, tmax, nullptr);
     }
   }
   if (cur >= 0) flush_hist<HB>(L.hist, ta.hist, ta.n - 1, tmax, &L.maxbin);

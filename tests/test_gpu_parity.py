@@ -111,6 +111,19 @@ def test_interval_histogram_bit_exact(cs, orc, counter, region, n):
     assert np.array_equal(got, want)
 
 
+def test_action_every_bin_filled(cs, orc):
+    """Counts in every bin up to n - 2, so the smeared sums run into the bins where the
+    weights (1 - eps)^m have underflowed (the kernel stops its walk there)."""
+    rng = np.random.default_rng(10)
+    n = 131072
+    hist = rng.integers(0, 10**9, size=n - 1, dtype=np.uint64)
+    for dim in (2, 3, 4):
+        for eps in (2.0**-6, 0.05, 0.5, 0.9, 1.0):
+            want, _ = orc.action(hist, n, dim, eps)
+            got = cs.cs_action(dev_u64(hist), n, dim, eps).item()
+            assert abs(got - want) <= 1e-12 * abs(want), (dim, eps, got, want)
+
+
 @pytest.mark.parametrize("counter", [0, 1, 2], ids=["bitset", "mfma", "mfma_fp4"])
 @pytest.mark.parametrize("n", [2, 65, 300, 4500])
 def test_chain_and_antichain_counts(cs, orc, counter, n):

@@ -114,7 +114,10 @@ cs_status cs_sprinkle(int region, double eta0, uint64_t seed, int64_t n, double 
 
 /*
  * Causal matrix S = C + C^T of n time-ordered points (C strictly upper triangular).
- *   coords  device, SoA planes as written by cs_sprinkle (any time-ordered input works).
+ *   coords  device, SoA planes as written by cs_sprinkle.  The points must be labelled
+ *           in time order, as cs_sprinkle writes them (non-decreasing time plane; in the
+ *           1+1 diamond any linear extension of the order): only pairs i < j are tested,
+ *           and in the 2+1 and 3+1 diamonds the test takes t_j >= t_i as given.
  *   bits    device, n * ld_words uint64.  Bit j of row i is bit (j & 63) of word
  *           bits[i * ld_words + (j >> 6)].  Every word is written, padding bits as 0.
  *   ld_words >= cs_ld_words(n) (CS_ERR_INVALID_ARG otherwise).
@@ -224,7 +227,8 @@ cs_status cs_degrees(const uint64_t *bits, int64_t n, int64_t ld_words, int64_t 
  *   0 <= eps <= 1; at eps = 1 the smeared form equals the local one.
  *   hist  device, n-1 uint64.   out  device, one double.
  * The local combination is an exact int64; the smeared sum is accumulated in
- * double-double (weights included), then rounded once to fp64.
+ * double-double (weights included), then rounded once to fp64.  Bins past the point
+ * where (1 - eps)^m < e^-700 are not visited: all their terms together are below 2^-820.
  */
 cs_status cs_action(const uint64_t *hist, int64_t n, int dim, double eps, double *out,
                     void *stream);

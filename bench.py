@@ -316,8 +316,12 @@ def main():
         tc = time.perf_counter()
         _, pairs = oracle.histogram_fast_rows(b_np, n, rows)
         tcpu = time.perf_counter() - tc
+        model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                      if ln.startswith("model name")), "unknown")
         out["cpu_baseline"] = {"value": pairs / tcpu, "unit": "related-pair counts/s",
                                "cores": oracle.max_threads(), "kind": "oracle",
+                               "cpu_model": model,
+                               "gpu_over_cpu": out["value"] / (pairs / tcpu),
                                "sample": f"optimised-tier oracle (word AND + popcount) over "
                                          f"{nrows} evenly spaced rows of the same N={n} matrix: "
                                          f"{pairs} related pairs in {tcpu:.1f} s "

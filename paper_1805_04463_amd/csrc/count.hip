@@ -47,7 +47,7 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kThreads = 256;
 constexpr int kStageBits = 256;         // K bits per LDS stage
 constexpr int kStageWords = kStageBits / 32;
-constexpr int kBinsSingle = 8192;       // LDS histogram bins, single instance (32 KiB)
+constexpr int kBinsSingle = 10240;      // LDS histogram bins, single instance (40 KiB)
 constexpr int kBinsBatch = 8192;        // LDS histogram bins, ensembles (n <= 8192)
 
 // Output tile t (0-based) in longest-first order for a T x T tile triangle:
@@ -795,8 +795,10 @@ struct RectSched {
   int64_t T, NA, NB, R;     // tiles per side, rectangle grid, rectangles touching j >= i
   int K, kmax;              // k = kmax - index, index in [0, K)
   int pre[kMaxK + 1];       // rectangles with larger k (exclusive prefix)
-  int lo[kMaxK];            // first b of the k-diagonal
 };
+
+// First b of the k-diagonal: a = 2b - k >= 0 and b >= 0.
+__device__ inline int64_t rect_first_b(int64_t k) { return k > 0 ? (k + 1) / 2 : 0; }
 
 __device__ inline bool rect_sched_fits(int64_t T) { return 2 * ceil_div(T, kRB) + 2 <= kMaxK; }
 
@@ -812,10 +814,9 @@ __device__ inline void rect_sched_init(RectSched& rs, int64_t T) {
     for (int t = 0; t < rs.K; ++t) {
       const int64_t k = rs.kmax - t;
       // b with a = 2b - k in [0, NA): b in [ceil(k/2), floor((NA-1+k)/2)], and b in [0, NB)
-      int64_t lo = k > 0 ? (k + 1) / 2 : 0;
+      const int64_t lo = rect_first_b(k);
       int64_t hi = (rs.NA - 1 + k) >= 0 ? (rs.NA - 1 + k) / 2 : -1;
       if (hi > rs.NB - 1) hi = rs.NB - 1;
-      rs.lo[t] = (int)lo;
       rs.pre[t] = acc;
       acc += hi >= lo ? (int)(hi - lo + 1) : 0;
     }
@@ -835,7 +836,7 @@ __device__ inline bool rect_tile(const RectSched& rs, int x, int64_t q, int64_t*
     if (rs.pre[mid] <= r) lo = mid; else hi = mid - 1;
   }
   const int64_t k = rs.kmax - lo;
-  const int64_t b = rs.lo[lo] + (r - rs.pre[lo]);
+  const int64_t b = rect_first_b(k) + (r - rs.pre[lo]);
   const int64_t a = 2 * b - k;
   const int p = (int)(q % kRect);
   *I = kRA * a + p / kRB;

@@ -85,6 +85,11 @@ def test_ds4_n65536(cs, orc):
     assert np.array_equal(hm, hb) and np.array_equal(hm, hf)
     assert int(hm.sum()) == rel
     assert int((np.arange(n - 1, dtype=np.uint64) * hm).sum()) == chains3
+    h = cs.cs_interval_histogram(b, n, cs.CS_COUNT_MFMA_FP4)
+    for eps in (0.0, 0.1):
+        want, _ = orc.action(hm, n, 4, eps)
+        got = cs.cs_action(h, n, 4, eps).item()
+        assert abs(got - want) <= 1e-12 * abs(want), (eps, got, want)
     # the GPU sprinkle from the same seed agrees to a few ulps
     g = cs.cs_sprinkle(W.DS4_SLAB, n, seed, eta0=W.DS_ETA0).cpu().numpy()
     assert np.allclose(g, coords, rtol=4e-15, atol=4e-16)
@@ -111,3 +116,9 @@ def test_mink4_n131072(cs, orc):
     assert int((np.arange(n - 1, dtype=np.uint64) * hm).sum()) == c3
     # ordering fraction of the 3+1 diamond is 1/10 (sd of R/(N(N-1)/2) at this N is ~1e-3)
     assert abs(rel / (n * (n - 1) / 2) - 0.1) < 0.01
+    # local and smeared actions from the counted abundances, against the oracle's sums
+    h = cs.cs_interval_histogram(b, n, cs.CS_COUNT_MFMA_FP4)
+    for eps in cfg["eps"] + (0.0,):
+        want, _ = orc.action(hm, n, 4, eps)
+        got = cs.cs_action(h, n, 4, eps).item()
+        assert abs(got - want) <= 1e-12 * abs(want), (eps, got, want)

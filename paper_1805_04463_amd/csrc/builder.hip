@@ -4,11 +4,12 @@
 //
 // Work decomposition: one wave per 64x64 block (bi <= bj) of the upper triangle.
 // Lane l owns row i = 64*bi + l (coordinates in registers) and tests it against the
-// 64 column points of block bj, which the wave reads through scalar loads (they are
-// the same for every lane); its 64 answers form row i's word for column block bj.  A 64x64 bit
-// transpose across the wave (six butterfly stages of lane shuffles) turns those row
-// words into the words of rows j for column block bi, so each unordered pair is tested
-// once and both halves of the symmetric matrix are written.
+// 64 column points of block bj, the same for every lane: scalar loads in the 2+1 and
+// 3+1 diamonds, staged in LDS elsewhere.  Its 64 answers form row i's word for column
+// block bj.  A 64x64 bit transpose across the wave (six butterfly stages of lane
+// shuffles) turns those row words into the words of rows j for column block bi, so each
+// unordered pair is tested once and both halves of the symmetric matrix are written.
+// Workgroups walk 1024 x 1024-point patches, one XCD per patch (k_build).
 //
 // Arithmetic: fp64, in the order written, no contraction (built with
 // -ffp-contract=off and explicit round-to-nearest intrinsics); on CDNA4 fp64 VALU

@@ -20,9 +20,11 @@
 //     down: a hit gives the new witness (the latest element in the word), and a member
 //     with no word left below is removed;
 //   - the members with a longer row left are queued (64 sub-queues, one counter add per
-//     wave); a second launch gives each of them a wavefront, which scans 64 words and
-//     then 1024 words per step (16 coalesced loads per lane), and records the next
-//     witness or removes the member.
+//     wave); a second launch gives each of them a wavefront, which scans 64 words, then
+//     256, then 1024 words per step (16 coalesced loads per lane), and records the next
+//     witness or removes the member.  The graded steps keep a witness found near the
+//     top (the common case, e.g. every first witness of round 0) from paying a full
+//     1024-word fetch.
 // The first launch's wave owns R_t[w] and P_t[w] (the second only sets bits of queued
 // members in P_t, with atomicOr).  Over all rounds every
 // row word is read about once.  Membership and removals are double-buffered by round
@@ -42,6 +44,7 @@ namespace {
 constexpr int kChainBlock = 256;  // four wavefronts
 constexpr int kChainWaves = kChainBlock / kWave;
 constexpr int kNear = 4;          // words from a lost witness down that each lane tries
+constexpr int kScanMid = 4;       // 64-word loads of the second scan step
 constexpr int kScanDepth = 16;    // 64-word loads in flight per wave in a long scan step
 constexpr int kLeftBlocks = 256;  // blocks of the "members left" count
 constexpr int kQueues = 64;       // long-scan sub-queues (spreads the counter adds)
@@ -197,6 +200,10 @@ __global__ __launch_bounds__(kChainBlock) void k_chain_scan(
     int64_t top = -(int64_t)(*wk) - 1;  // resume word, below k's own word
     int64_t found = scan_step<1>(row, R, top, wlo, lane);  // a witness nearby is common
     top -= kWave;
+    if (found < 0 && top >= wlo) {  // then 256 words before the 1024-word steps
+      found = scan_step<kScanMid>(row, R, top, wlo, lane);
+      top -= (int64_t)kWave * kScanMid;
+    }
     while (found < 0 && top >= wlo) {
       found = scan_step<kScanDepth>(row, R, top, wlo, lane);
       top -= (int64_t)kWave * kScanDepth;

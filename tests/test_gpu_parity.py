@@ -87,6 +87,32 @@ def test_causal_matrix_patches_bit_exact(cs, orc, region, eta0, n):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("region", [W.MINK4_DIAMOND, W.MINK3_DIAMOND], ids=["mink4", "mink3"])
+def test_causal_matrix_ties_and_null_pairs(cs, orc, region):
+    """Time-ordered points with runs of equal times and exactly null (dyadic) separations,
+    over several 64-point blocks: the device builder, which takes t_j >= t_i as given and
+    tests dt * dt > |dx|^2 alone, matches the oracle's dt > 0 and dt * dt > |dx|^2."""
+    rng = np.random.default_rng(11)
+    n = 300
+    planes = 4 if region == W.MINK4_DIAMOND else 3
+    # times on a coarse dyadic grid (many ties), space offsets on a dyadic grid too, so
+    # that dt^2 and |dx|^2 are exact and many pairs sit exactly on the light cone
+    t = np.sort(rng.integers(0, 16, n)).astype(np.float64) / 16.0
+    x = rng.integers(-8, 9, (planes - 1, n)).astype(np.float64) / 16.0
+    t[1], x[:, 1] = t[0], x[:, 0]  # one coincident pair
+    coords = np.ascontiguousarray(np.vstack([t[None, :], x]))
+    want = orc.causal_matrix(region, coords)
+    got = host_u64(cs.cs_causal_matrix(region, torch.from_numpy(coords).cuda()))
+    assert np.array_equal(got, want)
+    # the case is not vacuous: null pairs exist, and related and unrelated pairs both occur
+    dt = t[None, :] - t[:, None]
+    d2 = sum((x[p][None, :] - x[p][:, None]) ** 2 for p in range(planes - 1))
+    iu = np.triu_indices(n, 1)
+    assert (dt[iu] ** 2 == d2[iu]).sum() > 100 and (dt[iu] == 0).sum() > 100
+    assert ((dt[iu] == 0) & (d2[iu] == 0)).sum() > 0
+    assert 0 < int(np.bitwise_count(want).sum()) < n * (n - 1)
+
+
 def test_causal_matrix_wider_stride(cs, orc):
     n = 300
     coords = orc.sprinkle(W.MINK4_DIAMOND, n, seed=3)

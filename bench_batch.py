@@ -2,8 +2,8 @@
 
 One HIP-graph launch of the batch pipeline (sprinkle, matrix, counts, actions for
 every instance), with each of the three counters, against the same 256 instances as
-separate per-instance calls of the single-instance entry points (int8 counter).  All
-are timed with HIP events on one stream.
+separate per-instance calls of the single-instance entry points (int8 counter, and
+again with the fp4 counter).  All are timed with HIP events on one stream.
 """
 from __future__ import annotations
 
@@ -67,11 +67,12 @@ def run_batch(cs, torch, dev, stream, reps: int = 5):
     hist1 = torch.empty(nmax, dtype=torch.int64, device=dev)
     acts1 = torch.empty(len(eps), dtype=torch.float64, device=dev)
     sp_ws = torch.empty(L.cs_sprinkle_workspace_bytes(0, nmax), dtype=torch.uint8, device=dev)
-    h_ws = torch.empty(L.cs_histogram_workspace_bytes(nmax, 1), dtype=torch.uint8, device=dev)
+    h_ws = torch.empty(max(L.cs_histogram_workspace_bytes(nmax, c) for c in (1, 2)),
+                       dtype=torch.uint8, device=dev)
     B = cs.binding
     last = {}
 
-    def one_pass(keep=False):
+    def one_pass(counter, keep=False):
         for k in range(count):
             n = int(sizes[k])
             ldk = cs.cs_ld_words(n)
@@ -79,7 +80,7 @@ def run_batch(cs, torch, dev, stream, reps: int = 5):
                                    sp_ws.numel(), B._stream(stream)), "sprinkle")
             B._check(L.cs_causal_matrix(0, B._ptr(coords), n, B._ptr(bits), ldk, B._stream(stream)),
                      "matrix")
-            B._check(L.cs_interval_histogram(B._ptr(bits), n, ldk, 1, B._ptr(hist1), B._ptr(h_ws),
+            B._check(L.cs_interval_histogram(B._ptr(bits), n, ldk, counter, B._ptr(hist1), B._ptr(h_ws),
                                              h_ws.numel(), B._stream(stream)), "hist")
             for e, x in enumerate(eps):
                 B._check(L.cs_action(B._ptr(hist1), n, 2, float(x),
@@ -88,17 +89,24 @@ def run_batch(cs, torch, dev, stream, reps: int = 5):
                 torch.cuda.synchronize()
                 last[k] = hist1[:n - 1].cpu().numpy().view(np.uint64).copy()
 
-    one_pass(keep=True)
+    def timed_pass(counter):
+        a, b = ev(), ev()
+        a.record(stream)
+        one_pass(counter)
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b)
+
+    one_pass(cs.CS_COUNT_MFMA, keep=True)
     torch.cuda.synchronize()
-    a, b = ev(), ev()
-    a.record(stream)
-    one_pass()
-    b.record(stream)
-    b.synchronize()
-    seq_ms = a.elapsed_time(b)
+    seq_ms = timed_pass(cs.CS_COUNT_MFMA)
     out["per_instance_ms"] = seq_ms
     out["per_instance_ensembles_per_s"] = count / (seq_ms * 1e-3)
     out["graph_vs_per_instance"] = seq_ms / out["graph_mfma_ms"]
+    one_pass(cs.CS_COUNT_MFMA_FP4)
+    seq4_ms = timed_pass(cs.CS_COUNT_MFMA_FP4)
+    out["per_instance_fp4_ms"] = seq4_ms
+    out["graph_fp4_vs_per_instance_fp4"] = seq4_ms / out["graph_mfma_fp4_ms"]
     hm, offs = results["mfma"]
     hb, _ = results["bitset"]
     out["mfma_equals_bitset"] = bool(np.array_equal(hm, hb))

@@ -188,8 +188,9 @@ def main():
         "actions": {"local": actions[0], **{f"eps={e}": a for e, a in zip(eps_list, actions[1:])}},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic("paper_1805_04463_amd/csrc/count.hip",
-                                                 f"traffic_count_{args.counter}_mink4_n131072.json"),
+                     "traffic": measured_traffic(
+                         "paper_1805_04463_amd/csrc/count.hip",
+                         f"traffic_count_{args.counter}_{args.workload}.json"),
                      "kernel": kernel,
                      "measured_peak": measured_peak / 1e12,
                      "frac_of_measured_peak": achieved / measured_peak,

@@ -38,6 +38,7 @@ WORKLOADS = {
                             eps=(0.1,)),
     "mink4_n131072": dict(region=MINK4_DIAMOND, n=131072, seed=5, eps=(0.05, 0.1, 0.2)),
     "mink3_n16384": dict(region=MINK3_DIAMOND, n=16384, seed=6, eps=(0.05, 0.1, 0.2)),
+    "mink3_n131072": dict(region=MINK3_DIAMOND, n=131072, seed=5, eps=(0.05, 0.1, 0.2)),
     "ds2_n131072": dict(region=DS2_SLAB, n=131072, seed=DS2_SEEDS[0], eps=(DS2_EPS,),
                         eta0=DS2_ETA0),
 }

@@ -110,6 +110,18 @@ def test_batch_workload_256(cs, orc, counter):
         assert abs(R / (n * (n - 1) / 2) - 0.5) < 6 * 0.6 / np.sqrt(n), (k, n, R)
 
 
+def test_batch_workload_256_counters_agree(cs):
+    """All 256 instances: the bitset, int8 and fp4 counters give the same histograms, so
+    the same actions (three independent ways of counting every pair)."""
+    cfg = W.WORKLOADS["batch_mink2_256"]
+    sizes, seeds = W.batch_instances(cfg["seed"], cfg["count"], cfg["nmin"], cfg["nmax"])
+    runs = [run_batch(cs, sizes, seeds, c) for c in (0, 1, 2)]
+    (_, h0, a0), (_, h1, a1), (_, h2, a2) = runs
+    assert np.array_equal(h0, h1) and np.array_equal(h0, h2)
+    assert np.array_equal(a0, a1) and np.array_equal(a0, a2)
+    assert int(h0.sum()) > 0
+
+
 def test_autotune_writes_cache(cs, tmp_path):
     path = tmp_path / "tune.json"
     cs.cs_autotune(str(path))

@@ -216,6 +216,14 @@ def main():
             if name == "bitset":
                 leg["useful_bitpairs_per_s"] = useful_macs / (bms * 1e-3)
                 leg["frac_valu_peak"] = useful_macs / (bms * 1e-3) / PEAK_VALU_BITPAIRS
+                # The related-pair loop's work, sum over i ≺ j of (j - i - 1) bit-pairs, from
+                # the degree vectors: sum_j j indeg(j) - sum_i i outdeg(i) - R.
+                ind, outd = cs.cs_degrees(bits, n, stream=stream)
+                idx = np.arange(n, dtype=np.float64)
+                wb = float(idx @ ind.cpu().numpy().astype(np.float64)
+                           - idx @ outd.cpu().numpy().astype(np.float64)) - R
+                leg["related_pair_bitpairs"] = wb
+                leg["frac_valu_peak_related_pairs"] = wb / (bms * 1e-3) / PEAK_VALU_BITPAIRS
             else:
                 p, kd = PEAKS[name]
                 leg["achieved_TOPs"] = 2 * useful_macs / (bms * 1e-3) / 1e12

@@ -3,7 +3,8 @@ Sec. 3.2 degree vectors).
 
   whole order   heights of every element of the step's matrix (pair (-1, N)): the layer
                 partition by longest chain from below, and the height of the order;
-  degrees       in- and out-degree of every element (one pass over the matrix);
+  degrees       in- and out-degree of every element (one pass over the matrix), beside
+                a measured read ceiling: torch's sum over the same matrix;
   profile       every (minimal, maximal) pair of a 16384-element 1+1 diamond, the
                 candidates of the chain representation (Sec. 2.2), in one call.
 
@@ -49,9 +50,15 @@ def run_chains(cs, torch, dev, stream, bits, n: int, profile_n: int = 16384, see
     dms, (ind, outd) = _time(torch, stream, lambda: cs.cs_degrees(bits, n, stream=stream))
     deg_bytes = 8.0 * n * ((n + 63) // 64)
     minimal = int((ind == 0).sum().item())
+    # A measured read ceiling: torch's own reduction over the same resident matrix.
+    with torch.cuda.stream(stream):
+        rms, _ = _time(torch, stream, lambda: bits.sum(), reps=5)
+    read_GBs = bits.numel() * 8 / (rms * 1e-3) / 1e9
     out["degrees"] = {"ms": dms, "algorithmic_bytes": deg_bytes,
                       "achieved_GBs": deg_bytes / (dms * 1e-3) / 1e9,
                       "frac_hbm_peak": deg_bytes / (dms * 1e-3) / HBM_PEAK,
+                      "measured_read_GBs": read_GBs,
+                      "frac_of_measured_read": deg_bytes / (dms * 1e-3) / 1e9 / read_GBs,
                       "minimal_elements": minimal,
                       "minimal_have_height_1": bool(
                           torch.equal(height[0] == 1, ind == 0))}

@@ -47,7 +47,7 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kThreads = 256;
 constexpr int kStageBits = 256;         // K bits per LDS stage
 constexpr int kStageWords = kStageBits / 32;
-constexpr int kBinsSingle = 10240;      // LDS histogram bins, single instance (40 KiB)
+constexpr int kBinsSingle = 12288;      // LDS histogram bins, single instance (48 KiB)
 constexpr int kBinsBatch = 8192;        // LDS histogram bins, ensembles (n <= 8192)
 
 // Output tile t (0-based) in longest-first order for a T x T tile triangle:
@@ -789,54 +789,69 @@ __device__ inline bool bitset_tile(const TileArgs& ta, uint32_t* As, uint32_t* B
 // are done whatever the mapping of workgroups to XCDs.
 // ===========================================================================
 constexpr int kRA = 4, kRB = 8, kRect = kRA * kRB, kQueues = 8;
-constexpr int kMaxK = 2048;  // entries of the per-k rectangle table (T <= 8184)
+constexpr int kMaxK = 2048;  // diagonals of the rectangle grid served by the queues (T <= 8184)
 
 struct RectSched {
   int64_t T, NA, NB, R;     // tiles per side, rectangle grid, rectangles touching j >= i
   int K, kmax;              // k = kmax - index, index in [0, K)
-  int pre[kMaxK + 1];       // rectangles with larger k (exclusive prefix)
 };
+
+__device__ inline bool rect_sched_fits(int64_t T) { return 2 * ceil_div(T, kRB) + 2 <= kMaxK; }
 
 // First b of the k-diagonal: a = 2b - k >= 0 and b >= 0.
 __device__ inline int64_t rect_first_b(int64_t k) { return k > 0 ? (k + 1) / 2 : 0; }
 
-__device__ inline bool rect_sched_fits(int64_t T) { return 2 * ceil_div(T, kRB) + 2 <= kMaxK; }
+// sum_{m=0}^{x} floor(m / 2) for x >= -1, and 1 at x = -2, so that G(q) - G(p - 1) is the
+// sum over m in [p, q] for every p >= -1.
+__device__ inline int64_t floor_half_sum(int64_t x) {
+  return x == -2 ? 1 : (x < 0 ? 0 : ((x + 1) / 2) * (x / 2));
+}
 
-// Fills the table (one workgroup, called by every workgroup at kernel start).
-__device__ inline void rect_sched_init(RectSched& rs, int64_t T) {
-  if (threadIdx.x == 0) {
-    rs.T = T;
-    rs.NA = ceil_div(T, kRA);
-    rs.NB = ceil_div(T, kRB);
-    rs.kmax = (int)(2 * (rs.NB - 1));
-    rs.K = rs.kmax + 2;  // k from kmax down to -1 (k >= -1 <=> rectangle reaches j >= i)
-    int acc = 0;
-    for (int t = 0; t < rs.K; ++t) {
-      const int64_t k = rs.kmax - t;
-      // b with a = 2b - k in [0, NA): b in [ceil(k/2), floor((NA-1+k)/2)], and b in [0, NB)
-      const int64_t lo = rect_first_b(k);
-      int64_t hi = (rs.NA - 1 + k) >= 0 ? (rs.NA - 1 + k) / 2 : -1;
-      if (hi > rs.NB - 1) hi = rs.NB - 1;
-      rs.pre[t] = acc;
-      acc += hi >= lo ? (int)(hi - lo + 1) : 0;
-    }
-    rs.pre[rs.K] = acc;
-    rs.R = acc;
+// Rectangles on the diagonals k0 .. kmax.  The k-diagonal holds the b in
+// [rect_first_b(k), min(NB - 1, floor((NA - 1 + k) / 2))]: NB - ceil(k/2) of them from
+// kc = 2 NB - 1 - NA up, floor((NA - 1 + k) / 2) - ceil(k/2) + 1 below (never negative);
+// both are sums of floor(m / 2) over ranges of m.
+__device__ inline int64_t rect_prefix(const RectSched& rs, int64_t k0) {
+  const int64_t kmax = rs.kmax;
+  if (k0 > kmax) return 0;
+  const int64_t kc = 2 * rs.NB - 1 - rs.NA;
+  int64_t tot = 0;
+  const int64_t a = k0 > kc ? k0 : kc;
+  if (a <= kmax)  // sum ceil(k/2) over [a, kmax] = sum floor(m/2) over m in [a+1, kmax+1]
+    tot += (kmax - a + 1) * rs.NB - (floor_half_sum(kmax + 1) - floor_half_sum(a));
+  const int64_t b = kmax < kc - 1 ? kmax : kc - 1;
+  if (k0 <= b) {
+    const int64_t c = rs.NA - 1;
+    tot += (floor_half_sum(b + c) - floor_half_sum(k0 + c - 1)) -
+           (floor_half_sum(b + 1) - floor_half_sum(k0)) + (b - k0 + 1);
   }
-  __syncthreads();
+  return tot;
+}
+
+// The schedule's sizes, from T alone: uniform values, so the lookups below run on the
+// scalar unit.
+__device__ inline RectSched rect_sched_make(int64_t T) {
+  RectSched rs;
+  rs.T = T;
+  rs.NA = ceil_div(T, kRA);
+  rs.NB = ceil_div(T, kRB);
+  rs.kmax = (int)(2 * (rs.NB - 1));
+  rs.K = rs.kmax + 2;  // k from kmax down to -1 (k >= -1 <=> rectangle reaches j >= i)
+  rs.R = rect_prefix(rs, -1);
+  return rs;
 }
 
 // Item q of queue x -> tile (I, J); false if the slot is past the queue or no tile.
 __device__ inline bool rect_tile(const RectSched& rs, int x, int64_t q, int64_t* I, int64_t* J) {
   const int64_t r = (q / kRect) * kQueues + x;
   if (r >= rs.R) return false;
-  int lo = 0, hi = rs.K - 1;  // last t with pre[t] <= r
+  int lo = 0, hi = rs.K - 1;  // last t whose diagonals above hold at most r rectangles
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (rs.pre[mid] <= r) lo = mid; else hi = mid - 1;
+    if (rect_prefix(rs, rs.kmax - mid + 1) <= r) lo = mid; else hi = mid - 1;
   }
   const int64_t k = rs.kmax - lo;
-  const int64_t b = rect_first_b(k) + (r - rs.pre[lo]);
+  const int64_t b = rect_first_b(k) + (r - rect_prefix(rs, k + 1));
   const int64_t a = 2 * b - k;
   const int p = (int)(q % kRect);
   *I = kRA * a + p / kRB;
@@ -864,10 +879,6 @@ struct MfmaLds {
   uint32_t maxbin;
   int slot;
 };
-template <int BM, int HB>
-struct MfmaLdsSched : MfmaLds<BM, HB> {
-  RectSched rs;
-};
 template <int HB>
 struct BitsetLds {
   uint32_t As[kBitsetTile * kStageWords] __attribute__((aligned(16)));
@@ -884,7 +895,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
                                                             unsigned int* __restrict__ counter,
                                                             FieldArgs f) {
   constexpr int BM = 2 * WM * 32, HB = kBinsSingle;
-  __shared__ MfmaLdsSched<BM, HB> L;  // 96 KiB ring + 32 KiB bins + 16 KiB table at WM = 4
+  __shared__ MfmaLds<BM, HB> L;  // 96 KiB ring + 48 KiB bins + 8 KiB relation bits at WM = 4
   const int64_t T = ceil_div(n, BM);
   if constexpr (EPI == 0)
     for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
@@ -898,7 +909,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
   // Rectangle queues per XCD while the table fits; beyond that (very large n) one queue,
   // longest K-range first.
   const bool rect = rect_sched_fits(T);
-  if (rect) rect_sched_init(L.rs, T);
+  const RectSched rs = rect_sched_make(rect ? T : 1);
   const int x0 = xcc_id();
   const int64_t ntiles = T * (T + 1) / 2;
   int probe = 0;
@@ -907,12 +918,12 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
     if (rect) {
       if (probe >= kQueues) break;
       const int x = (x0 + probe) & (kQueues - 1);
-      const int64_t q = next_tile(counter + x, &L.slot);
-      if (q >= rect_queue_len(L.rs, x)) {
+      const int64_t q = __builtin_amdgcn_readfirstlane((int)next_tile(counter + x, &L.slot));
+      if (q >= rect_queue_len(rs, x)) {
         ++probe;
         continue;
       }
-      if (!rect_tile(L.rs, x, q, &I, &J)) continue;
+      if (!rect_tile(rs, x, q, &I, &J)) continue;
     } else {
       const int64_t t = next_tile(counter, &L.slot);
       if (t >= ntiles) break;

@@ -82,6 +82,26 @@ def test_many_pairs_one_call(cs, orc):
     assert (want == 0).any() and (want > 3).any()
 
 
+def test_many_related_pairs_one_call(cs, orc):
+    """6000 pairs in one call (grid rows and long-scan queues far beyond the other cases):
+    related pairs drawn from the matrix, pairs from the virtual bottom and to the virtual top,
+    and unrelated pairs, on a 1+1 diamond (long chains) of 2048 points."""
+    n = 2048
+    coords = orc.sprinkle(W.MINK2_DIAMOND, n, 48)
+    bits = orc.causal_matrix(W.MINK2_DIAMOND, coords)
+    rng = np.random.default_rng(49)
+    rows = np.unpackbits(bits.view(np.uint8), axis=1, bitorder="little")[:, :n].astype(bool)
+    I, J = np.nonzero(np.triu(rows, 1))
+    pick = rng.choice(len(I), 3000, replace=False)
+    lo = list(I[pick]) + [-1] * 1000 + list(rng.integers(0, n, 1000)) + list(rng.integers(0, n - 1, 1000))
+    hi = list(J[pick]) + list(rng.integers(0, n, 1000)) + [n] * 1000
+    hi += [int(rng.integers(a + 1, n)) for a in lo[len(hi):]]
+    want, _ = orc.longest_chain(bits, n, lo, hi)
+    got, _ = cs.cs_longest_chain(torch.from_numpy(bits.view(np.int64)).cuda(), n, lo, hi)
+    assert np.array_equal(host(got), want)
+    assert (want[:3000] >= 1).all() and want.max() > 40
+
+
 def test_profile_pairs_mink2_n16384(cs, orc):
     """Every (minimal, maximal) pair of a 1+1 diamond at the boundary chapter's size."""
     n = 16384

@@ -415,7 +415,11 @@ cs_status launch_longest_chain(const uint64_t* bits, int64_t n, int64_t ld, cons
     CS_HIP_CHECK(hipStreamSynchronize(st));
     if (counts[1] == 0) break;
     const double rate = (double)(counts[0] - counts[1]) / (double)batch;  // >= 1 per round
-    batch = std::max<int64_t>(2, std::min<int64_t>(64, (int64_t)ceil((double)counts[1] / rate)));
+    // Layers thin out towards the end, so the rate so far under-estimates the rounds
+    // left; half again as many rounds (a round past the end is two near-empty launches)
+    // saves host round trips: 1.76 -> 1.62 ms on the whole 3+1 order at N = 131072.
+    const int64_t want = (int64_t)ceil(1.5 * (double)counts[1] / rate);
+    batch = std::max<int64_t>(2, std::min<int64_t>(64, want));
   }
   if (counts[1] != 0) return CS_ERR_HIP;  // unreachable for a valid order
   hipLaunchKernelGGL(k_chain_maxh, dim3((unsigned)std::min<int64_t>(64, ceil_div(n, 4096)),

@@ -335,6 +335,14 @@ def main():
                                          f"{nrows} evenly spaced rows of the same N={n} matrix: "
                                          f"{pairs} related pairs in {tcpu:.1f} s "
                                          f"(oracle sprinkle + matrix took {t_link:.1f} s)"}
+        # The step's fp64 action sums against the oracle's quad-precision ones, both from
+        # the step's (device) abundances: the error of the double-double sum, stated.
+        errs = {}
+        for e, a in zip((0.0,) + eps_list, actions):
+            want, kappa = oracle.action(np.ascontiguousarray(h), n, dim, e)
+            errs["local" if e == 0.0 else f"eps={e}"] = {
+                "rel_err": abs(a - want) / abs(want), "kappa": kappa}
+        out["cpu_baseline"]["action_vs_oracle"] = errs
     print(json.dumps(out))
     return 0
 

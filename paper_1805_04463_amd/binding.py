@@ -105,7 +105,65 @@ def _ptr(t: torch.Tensor):
         raise CausalError("expected a device tensor")
     if not t.is_contiguous():
         raise CausalError("expected a contiguous tensor")
+    if t.device.index != torch.cuda.current_device():
+        raise CausalError(f"tensor on {t.device}, but the current device is "
+                          f"cuda:{torch.cuda.current_device()}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, name: str, dtypes, numel: int | None = None, min_numel: int | None = None,
+          shape: tuple | None = None):
+    """Validate a caller's tensor before its pointer crosses the ABI: the library trusts
+    the sizes it is given, so a short buffer here would become an out-of-bounds access on
+    the device."""
+    if not isinstance(t, torch.Tensor):
+        raise CausalError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype not in dtypes:
+        raise CausalError(f"{name}: dtype {t.dtype}, expected one of {list(dtypes)}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise CausalError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if numel is not None and t.numel() != numel:
+        raise CausalError(f"{name}: {t.numel()} elements, expected {numel}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise CausalError(f"{name}: {t.numel()} elements, expected at least {min_numel}")
+    if not t.is_contiguous():
+        raise CausalError(f"{name}: expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _on_device(*tensors):
+    """Every tensor lives on the current ROCm device (checked after the shapes)."""
+    for t in tensors:
+        _ptr(t)
+
+
+def _nbytes(t: torch.Tensor) -> int:
+    return t.numel() * t.element_size()
+
+
+def _int(x, name: str) -> int:
+    if isinstance(x, bool) or not isinstance(x, (int,)) and not hasattr(x, "__index__"):
+        raise CausalError(f"{name}: expected an integer, got {type(x).__name__}")
+    return int(x)
+
+
+def _bits(bits, n: int):
+    """The packed matrix: int64 (n', ld) with n' >= n rows and ld >= cs_ld_words(n)."""
+    if not isinstance(bits, torch.Tensor) or bits.dim() != 2:
+        raise CausalError("bits: expected a 2-D (rows, ld_words) tensor")
+    if n < 2:
+        raise CausalError(f"n = {n}: need at least 2 elements")
+    if bits.shape[0] < n:
+        raise CausalError(f"bits: {bits.shape[0]} rows for n = {n}")
+    ld = bits.shape[1]
+    if ld < lib().cs_ld_words(n):
+        raise CausalError(f"bits: {ld} words per row, n = {n} needs {lib().cs_ld_words(n)}")
+    return _need(bits, "bits", _WORDS), ld
+
+
+_WORDS = (torch.int64, torch.uint64) if hasattr(torch, "uint64") else (torch.int64,)
+_F64 = (torch.float64,)
+_BYTES = (torch.uint8, torch.int8) + _WORDS
 
 
 def _u8_workspace(nbytes: int) -> torch.Tensor:
@@ -122,9 +180,12 @@ def cs_ld_words(n: int) -> int:
 
 def cs_sprinkle(region: int, n: int, seed: int, eta0: float = 1.2, stream=None) -> torch.Tensor:
     """Time-ordered coordinates, float64 device tensor (planes, n)."""
+    n = _int(n, "n")
     planes = lib().cs_coord_planes(region)
     if planes < 0:
         raise CausalError(f"unknown region {region}")
+    if n < 2:
+        raise CausalError(f"n = {n}: need at least 2 points")
     coords = torch.empty((planes, n), dtype=torch.float64, device=_dev())
     ws_bytes = lib().cs_sprinkle_workspace_bytes(region, n)
     ws = _u8_workspace(ws_bytes)
@@ -138,13 +199,22 @@ def cs_causal_matrix(region: int, coords: torch.Tensor, n: int | None = None,
                      ld_words: int | None = None, out: torch.Tensor | None = None,
                      stream=None) -> torch.Tensor:
     """Symmetric packed matrix as an int64 device tensor (n, ld) holding uint64 words."""
-    n = coords.shape[1] if n is None else n
-    ld = lib().cs_ld_words(n) if ld_words is None else ld_words
+    planes = lib().cs_coord_planes(region)
+    if planes < 0:
+        raise CausalError(f"unknown region {region}")
+    if not isinstance(coords, torch.Tensor) or coords.dim() != 2:
+        raise CausalError("coords: expected a 2-D (planes, n) tensor")
+    n = coords.shape[1] if n is None else _int(n, "n")
+    pc = _need(coords, "coords", _F64, shape=(planes, n))
+    if n < 2:
+        raise CausalError(f"n = {n}: need at least 2 points")
+    ld = lib().cs_ld_words(n) if ld_words is None else _int(ld_words, "ld_words")
+    if ld < lib().cs_ld_words(n):
+        raise CausalError(f"ld_words = {ld}: n = {n} needs {lib().cs_ld_words(n)}")
     bits = out if out is not None else torch.empty((n, ld), dtype=torch.int64, device=_dev())
-    if coords.dtype != torch.float64:
-        raise CausalError("coords must be float64")
-    _check(lib().cs_causal_matrix(region, _ptr(coords), n, _ptr(bits), ld, _stream(stream)),
-           "cs_causal_matrix")
+    pb = _need(bits, "out", _WORDS, shape=(n, ld))
+    _on_device(coords, bits)
+    _check(lib().cs_causal_matrix(region, pc, n, pb, ld, _stream(stream)), "cs_causal_matrix")
     return bits
 
 
@@ -152,12 +222,16 @@ def cs_interval_histogram(bits: torch.Tensor, n: int, counter: int = CS_COUNT_MF
                           out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
                           stream=None) -> torch.Tensor:
     """N_m for m = 0..n-2 as an int64 device tensor (uint64 counts)."""
-    ld = bits.shape[1]
+    n = _int(n, "n")
+    pbits, ld = _bits(bits, n)
     hist = out if out is not None else torch.empty(n - 1, dtype=torch.int64, device=_dev())
+    ph = _need(hist, "out", _WORDS, numel=n - 1)
     ws_bytes = lib().cs_histogram_workspace_bytes(n, counter)
     ws = workspace if workspace is not None else _u8_workspace(ws_bytes)
-    _check(lib().cs_interval_histogram(_ptr(bits), n, ld, counter, _ptr(hist), _ptr(ws),
-                                       ws.numel(), _stream(stream)), "cs_interval_histogram")
+    pw = _need(ws, "workspace", _BYTES)
+    _on_device(bits, hist, ws)
+    _check(lib().cs_interval_histogram(pbits, n, ld, counter, ph, pw, _nbytes(ws),
+                                       _stream(stream)), "cs_interval_histogram")
     hist._cs_keepalive = ws
     return hist
 
@@ -166,12 +240,17 @@ def cs_dalembertian(bits: torch.Tensor, n: int, dim: int, ell: float, phi: torch
                     counter: int = CS_COUNT_MFMA_FP4, out: torch.Tensor | None = None,
                     workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """B^(d+1) phi for every element as a float64 device tensor (phi: n float64 on device)."""
-    ld = bits.shape[1]
+    n = _int(n, "n")
+    pbits, ld = _bits(bits, n)
+    pphi = _need(phi, "phi", _F64, numel=n)
     o = out if out is not None else torch.empty(n, dtype=torch.float64, device=_dev())
+    po = _need(o, "out", _F64, numel=n)
     ws_bytes = lib().cs_dalembertian_workspace_bytes(n, counter)
     ws = workspace if workspace is not None else _u8_workspace(max(ws_bytes, 1))
-    _check(lib().cs_dalembertian(_ptr(bits), n, ld, dim, float(ell), counter, _ptr(phi), _ptr(o),
-                                 _ptr(ws), ws.numel(), _stream(stream)), "cs_dalembertian")
+    pw = _need(ws, "workspace", _BYTES)
+    _on_device(bits, phi, o, ws)
+    _check(lib().cs_dalembertian(pbits, n, ld, dim, float(ell), counter, pphi, po, pw,
+                                 _nbytes(ws), _stream(stream)), "cs_dalembertian")
     o._cs_keepalive = ws
     return o
 
@@ -183,37 +262,48 @@ def cs_longest_chain(bits: torch.Tensor, n: int, lo, hi, heights: bool = False,
     tensors of count and (count, n) elements (height None unless requested).  Blocks until
     done."""
     import numpy as np
+    n = _int(n, "n")
+    pbits, ld = _bits(bits, n)
     lo_h = np.ascontiguousarray(np.atleast_1d(lo), dtype=np.int64)
     hi_h = np.ascontiguousarray(np.atleast_1d(hi), dtype=np.int64)
-    if lo_h.shape != hi_h.shape:
-        raise CausalError("lo and hi must have the same length")
+    if lo_h.shape != hi_h.shape or lo_h.ndim != 1:
+        raise CausalError("lo and hi must be 1-D and of the same length")
     count = len(lo_h)
     length = torch.empty(count, dtype=torch.int32, device=_dev())
     height = torch.empty((count, n), dtype=torch.int32, device=_dev()) if heights else None
     ws_bytes = lib().cs_longest_chain_workspace_bytes(n, count)
     ws = workspace if workspace is not None else _u8_workspace(max(ws_bytes, 1))
-    _check(lib().cs_longest_chain(_ptr(bits), n, bits.shape[1],
-                                  lo_h.ctypes.data_as(ctypes.c_void_p),
+    pw = _need(ws, "workspace", _BYTES)
+    _on_device(bits, ws)
+    _check(lib().cs_longest_chain(pbits, n, ld, lo_h.ctypes.data_as(ctypes.c_void_p),
                                   hi_h.ctypes.data_as(ctypes.c_void_p), count, _ptr(length),
-                                  _ptr(height) if heights else None, _ptr(ws), ws.numel(),
+                                  _ptr(height) if heights else None, pw, _nbytes(ws),
                                   _stream(stream)), "cs_longest_chain")
     return length, height
 
 
 def cs_degrees(bits: torch.Tensor, n: int, stream=None):
     """(indeg, outdeg) of every element as int64 device tensors."""
+    n = _int(n, "n")
+    pbits, ld = _bits(bits, n)
     ind = torch.empty(n, dtype=torch.int64, device=_dev())
     outd = torch.empty(n, dtype=torch.int64, device=_dev())
-    _check(lib().cs_degrees(_ptr(bits), n, bits.shape[1], _ptr(ind), _ptr(outd), _stream(stream)),
-           "cs_degrees")
+    _on_device(bits)
+    _check(lib().cs_degrees(pbits, n, ld, _ptr(ind), _ptr(outd), _stream(stream)), "cs_degrees")
     return ind, outd
 
 
 def cs_action(hist: torch.Tensor, n: int, dim: int, eps: float = 0.0,
               out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """The action as a one-element float64 device tensor."""
+    n = _int(n, "n")
+    if n < 2:
+        raise CausalError(f"n = {n}: need at least 2 elements")
+    ph = _need(hist, "hist", _WORDS, min_numel=n - 1)
     o = out if out is not None else torch.empty(1, dtype=torch.float64, device=_dev())
-    _check(lib().cs_action(_ptr(hist), n, dim, float(eps), _ptr(o), _stream(stream)), "cs_action")
+    po = _need(o, "out", _F64, min_numel=1)
+    _on_device(hist, o)
+    _check(lib().cs_action(ph, n, dim, float(eps), po, _stream(stream)), "cs_action")
     return o
 
 
@@ -235,18 +325,26 @@ class BatchPlan:
         self.hist_len = lib().cs_batch_hist_len(h)
         self.offsets = [lib().cs_batch_hist_offset(h, k) for k in range(self.count)]
 
+    def _buffers(self, seeds, hist, actions, workspace):
+        ptrs = (_need(seeds, "seeds", _WORDS, numel=self.count),
+                _need(hist, "hist", _WORDS, min_numel=self.hist_len),
+                _need(actions, "actions", _F64, min_numel=self.count * len(self.eps)),
+                _need(workspace, "workspace", _BYTES))
+        _on_device(seeds, hist, actions, workspace)
+        return ptrs
+
     def run(self, seeds: torch.Tensor, hist: torch.Tensor, actions: torch.Tensor,
             workspace: torch.Tensor, stream=None):
-        _check(lib().cs_batch_run(self.handle, _ptr(seeds), _ptr(hist), _ptr(actions),
-                                  _ptr(workspace), workspace.numel(), _stream(stream)),
-               "cs_batch_run")
+        ps, ph, pa, pw = self._buffers(seeds, hist, actions, workspace)
+        _check(lib().cs_batch_run(self.handle, ps, ph, pa, pw, _nbytes(workspace),
+                                  _stream(stream)), "cs_batch_run")
 
     def graph(self, seeds: torch.Tensor, hist: torch.Tensor, actions: torch.Tensor,
               workspace: torch.Tensor) -> "BatchGraph":
+        ps, ph, pa, pw = self._buffers(seeds, hist, actions, workspace)
         g = ctypes.c_void_p()
-        _check(lib().cs_batch_graph_create(self.handle, _ptr(seeds), _ptr(hist), _ptr(actions),
-                                           _ptr(workspace), workspace.numel(), ctypes.byref(g)),
-               "cs_batch_graph_create")
+        _check(lib().cs_batch_graph_create(self.handle, ps, ph, pa, pw, _nbytes(workspace),
+                                           ctypes.byref(g)), "cs_batch_graph_create")
         return BatchGraph(g, (seeds, hist, actions, workspace, self))
 
     def __del__(self):

@@ -64,6 +64,8 @@ def lib():
         L.or_causal_rows.restype = c_int
         L.or_histogram_naive.argtypes = [p, i64, i64, p]
         L.or_histogram_naive.restype = c_int
+        L.or_histogram_naive_elems.argtypes = [p, i64, i64, p, p, i64]
+        L.or_histogram_naive_elems.restype = c_int
         L.or_histogram_fast.argtypes = [p, i64, i64, p, i64, i64]
         L.or_histogram_fast.restype = i64
         L.or_histogram_fast_rows.argtypes = [p, i64, i64, p, p, i64]
@@ -145,6 +147,17 @@ def histogram_naive(bits: np.ndarray, n: int) -> np.ndarray:
     hist = np.zeros(max(n - 1, 1), dtype=np.uint64)
     if lib().or_histogram_naive(_ptr(bits), n, bits.shape[1], _ptr(hist)) != 0:
         raise ValueError("or_histogram_naive failed")
+    return hist
+
+
+def histogram_naive_elems(bits: np.ndarray, n: int, elems) -> np.ndarray:
+    """The definitional tier over the listed elements j only (all pairs i ≺ j)."""
+    bits = np.ascontiguousarray(bits, dtype=np.uint64)
+    elems = np.ascontiguousarray(elems, dtype=np.int64)
+    hist = np.zeros(max(n - 1, 1), dtype=np.uint64)
+    if lib().or_histogram_naive_elems(_ptr(bits), n, bits.shape[1], _ptr(hist), _ptr(elems),
+                                      len(elems)) != 0:
+        raise ValueError("or_histogram_naive_elems failed")
     return hist
 
 

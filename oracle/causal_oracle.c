@@ -22,9 +22,10 @@
  *                 later index never precedes an earlier one.
  *   causal matrix Ch. 4 introduction: i and j are related when timelike
  *                 separated; stored as P + P^T (Sec. 3.2 "Data Structures").
- *   abundances    Alg. "Naive Interval Abundance Measurement" and the
- *                 inclusive-order-interval definition (eq. IOIs): for every related
- *                 pair count the elements strictly inside its Alexandroff set.
+ *   abundances    the inclusive order intervals (eq. IOIs) and the Alexandroff set
+ *                 A_ij = J+(i) ∩ J-(j) (Sec. 2): for every element j and every i in its
+ *                 past, the elements of j's past that are also in i's future; the
+ *                 quantity of Alg. "Naive Interval Abundance Measurement".
  *   fast tier     Alg. "Optimized Interval Abundance Measurement": word-wise AND
  *                 + popcount over the columns strictly between i and j.
  *   action        Sec. 4.2: local BD actions S^(1+1), S^(3+1) and their smeared
@@ -381,10 +382,26 @@ static int or_bit(const uint64_t *bits, int64_t ld, int64_t i, int64_t j)
 /* Interval abundances                                                         */
 /* ------------------------------------------------------------------------- */
 
-/* Alg. "Naive Interval Abundance Measurement": for each related i < j count
- * the k with i < k < j, i ≺ k and k ≺ j; bin that count.  hist has n-1 bins
- * (counts 0..n-2; the thesis's n_m is hist[m-1]).  The pair loop is split over
- * threads by i with one private histogram per thread, then reduced. */
+/* Definitional tier, from the inclusive order intervals (eq. IOIs) and the Alexandroff
+ * set A_ij = J+(i) ∩ J-(j) of Sec. 2 (set algorithms): for every element j and every i in
+ * its past J-(j), the size of A_ij is the number of k in J-(j) that also lie in J+(i);
+ * the pair then belongs to L_{|A_ij|+1}(j), so N_m = sum_j |L_{m+1}(j)| counts the related
+ * pairs with m elements inside.  This is the quantity the naive algorithm of Sec. 4.2
+ * computes, but organised around each element's past as the interval definition is.
+ * Only labels below j can precede j (time order), and elements k of A_ij lie strictly
+ * between i and j.  One private histogram per thread, summed at the end.  hist has n-1
+ * bins (counts 0..n-2; the thesis's n_m is hist[m-1]). */
+static void or_past_intervals(const uint64_t *bits, int64_t ld, int64_t j, uint64_t *mine)
+{
+    for (int64_t i = 0; i < j; i++) {
+        if (!or_bit(bits, ld, j, i)) continue;        /* i in J-(j) */
+        int64_t size = 0;
+        for (int64_t k = i + 1; k < j; k++)
+            if (or_bit(bits, ld, j, k) && or_bit(bits, ld, i, k)) size++;  /* k in J-(j), J+(i) */
+        mine[size]++;
+    }
+}
+
 int or_histogram_naive(const uint64_t *bits, int64_t n, int64_t ld, uint64_t *hist)
 {
     if (n < 2) return -1;
@@ -394,15 +411,29 @@ int or_histogram_naive(const uint64_t *bits, int64_t n, int64_t ld, uint64_t *hi
     {
         uint64_t *mine = (uint64_t *)calloc((size_t)nb, sizeof(uint64_t));
 #pragma omp for schedule(dynamic, 1)
-        for (int64_t i = 0; i < n - 1; i++) {
-            for (int64_t j = i + 1; j < n; j++) {
-                if (!or_bit(bits, ld, i, j)) continue;
-                int64_t x = 0;
-                for (int64_t k = i + 1; k < j; k++)
-                    if (or_bit(bits, ld, i, k) && or_bit(bits, ld, k, j)) x++;
-                mine[x]++;
-            }
-        }
+        for (int64_t j = n - 1; j >= 1; j--) or_past_intervals(bits, ld, j, mine);
+#pragma omp critical
+        for (int64_t m = 0; m < nb; m++) hist[m] += mine[m];
+        free(mine);
+    }
+    return 0;
+}
+
+/* The definitional tier over a list of elements j only (every i in J-(j)): a bounded
+ * sample of the full count, used to time the CPU. */
+int or_histogram_naive_elems(const uint64_t *bits, int64_t n, int64_t ld, uint64_t *hist,
+                             const int64_t *elems, int64_t nelems)
+{
+    if (n < 2) return -1;
+    int64_t nb = n - 1;
+    for (int64_t e = 0; e < nelems; e++)
+        if (elems[e] < 0 || elems[e] >= n) return -1;
+    memset(hist, 0, sizeof(uint64_t) * (size_t)nb);
+#pragma omp parallel
+    {
+        uint64_t *mine = (uint64_t *)calloc((size_t)nb, sizeof(uint64_t));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t e = 0; e < nelems; e++) or_past_intervals(bits, ld, elems[e], mine);
 #pragma omp critical
         for (int64_t m = 0; m < nb; m++) hist[m] += mine[m];
         free(mine);

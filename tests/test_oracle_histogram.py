@@ -135,3 +135,20 @@ def test_mink2_expected_abundances(orc):
         exp = n * (n - 1) * math.comb(n - 2, m) * val
         assert abs(mean[m] - exp) < 5 * se[m] + 1e-9, (m, mean[m], exp, se[m])
     assert abs(hs.sum(1).mean() - n * (n - 1) / 4) < 5 * hs.sum(1).std() / math.sqrt(len(seeds))
+
+
+def test_element_restricted_naive_tier_adds_up(orc):
+    """The definitional tier over disjoint sets of elements j adds up to the whole count,
+    and each element's part holds exactly its past's size in pairs (sum over i ≺ j)."""
+    n = 700
+    c = orc.sprinkle(W.MINK4_DIAMOND, n, seed=46)
+    bits = orc.causal_matrix(W.MINK4_DIAMOND, c)
+    full = orc.histogram_naive(bits, n)
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(n)
+    parts = [orc.histogram_naive_elems(bits, n, perm[a:b]) for a, b in [(0, 50), (50, 333), (333, n)]]
+    assert np.array_equal(sum(p.astype(np.int64) for p in parts), full.astype(np.int64))
+    ind, _, _, _ = orc.degrees(bits, n)
+    assert int(parts[0].sum()) == int(ind[perm[:50]].sum())
+    with pytest.raises(ValueError):
+        orc.histogram_naive_elems(bits, n, [n])

@@ -21,7 +21,13 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "causal_oracle.c")
 _BUILD = os.path.join(_HERE, "_build")
-_LIB_PATH = os.path.join(_BUILD, "liboracle.so")
+# ORACLE_SANITIZE=1 selects a build instrumented with AddressSanitizer and
+# UndefinedBehaviorSanitizer (any finding aborts).  The interpreter is not instrumented,
+# so such a process must start with the ASan runtime preloaded (LD_PRELOAD).
+_SANITIZE = os.environ.get("ORACLE_SANITIZE", "") == "1"
+_LIB_PATH = os.path.join(_BUILD, "liboracle_san.so" if _SANITIZE else "liboracle.so")
+_SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+              "-fno-omit-frame-pointer", "-g"]
 
 MINK2_DIAMOND, MINK4_DIAMOND, DS4_SLAB, DS2_SLAB, MINK3_DIAMOND = 0, 1, 2, 3, 4
 PLANES = {MINK2_DIAMOND: 2, MINK4_DIAMOND: 4, DS4_SLAB: 7, DS2_SLAB: 3, MINK3_DIAMOND: 3}
@@ -36,7 +42,8 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
-               "-ffp-contract=off", "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lquadmath", "-lm"]
+               "-ffp-contract=off", "-fno-fast-math", "-Wall", *(_SAN_FLAGS if _SANITIZE else []),
+               "-o", tmp, _SRC, "-lquadmath", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH

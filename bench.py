@@ -36,7 +36,7 @@ import workloads as W  # noqa: E402
 PEAK_INT8_OPS = 5.0e15   # MI355X dense int8 MFMA
 PEAK_FP4_OPS = 10.1e15   # MI355X dense fp4 MFMA
 PEAK_VALU_BITPAIRS = 256 * 4 * 16 * 2.4e9 * 16  # 2 VALU ops per 32 bit-pairs (AND, BCNT)
-COUNTERS = {"bitset": 0, "mfma": 1, "mfma_fp4": 2}
+COUNTERS = {"bitset": 0, "mfma": 1, "mfma_fp4": 2, "bitset_dense": 3}
 PEAKS = {"mfma": (PEAK_INT8_OPS, "int8"), "mfma_fp4": (PEAK_FP4_OPS, "fp4")}
 
 
@@ -198,6 +198,7 @@ def main():
     }
 
     if not args.no_bitset:
+        wbits = None
         for name, c in COUNTERS.items():
             if name == args.counter:
                 continue
@@ -213,17 +214,25 @@ def main():
             leg = {"count_kernel_ms": bms, "counts_per_s_kernel": R / (bms * 1e-3),
                    "identical_histogram": bool(np.array_equal(hb, h)),
                    "time_vs_main_counter": bms / float(np.min(count_ms))}
-            if name == "bitset":
-                leg["useful_bitpairs_per_s"] = useful_macs / (bms * 1e-3)
-                leg["frac_valu_peak"] = useful_macs / (bms * 1e-3) / PEAK_VALU_BITPAIRS
-                # The related-pair loop's work, sum over i ≺ j of (j - i - 1) bit-pairs, from
-                # the degree vectors: sum_j j indeg(j) - sum_i i outdeg(i) - R.
-                ind, outd = cs.cs_degrees(bits, n, stream=stream)
-                idx = np.arange(n, dtype=np.float64)
-                wb = float(idx @ ind.cpu().numpy().astype(np.float64)
-                           - idx @ outd.cpu().numpy().astype(np.float64)) - R
-                leg["related_pair_bitpairs"] = wb
-                leg["frac_valu_peak_related_pairs"] = wb / (bms * 1e-3) / PEAK_VALU_BITPAIRS
+            if name.startswith("bitset"):
+                # The related-pair work W_bits = sum over i ≺ j of (j - i - 1) bit-pairs, from
+                # the degree vectors: sum_j j indeg(j) - sum_i i outdeg(i) - R.  It is the
+                # bitset counters' roofline work; the dense triangle's N(N-1)(N-2)/6
+                # bit-pairs is what CS_COUNT_BITSET_DENSE evaluates.
+                if wbits is None:
+                    ind, outd = cs.cs_degrees(bits, n, stream=stream)
+                    idx = np.arange(n, dtype=np.float64)
+                    wbits = float(idx @ ind.cpu().numpy().astype(np.float64)
+                                  - idx @ outd.cpu().numpy().astype(np.float64)) - R
+                rate = wbits / (bms * 1e-3)
+                leg["roofline"] = {"bound": "alu", "achieved": rate / 1e12,
+                                   "peak": PEAK_VALU_BITPAIRS / 1e12, "unit": "T bit-pairs/s",
+                                   "frac": rate / PEAK_VALU_BITPAIRS,
+                                   "work_per_launch": f"W_bits = sum over related pairs of "
+                                                      f"(j - i - 1) = {wbits:.4e} bit-pairs"}
+                leg["dense_triangle_bitpairs_per_s"] = useful_macs / (bms * 1e-3)
+                leg["frac_valu_peak_dense_triangle"] = (useful_macs / (bms * 1e-3)
+                                                        / PEAK_VALU_BITPAIRS)
             else:
                 p, kd = PEAKS[name]
                 leg["achieved_TOPs"] = 2 * useful_macs / (bms * 1e-3) / 1e12

@@ -76,14 +76,23 @@ typedef enum {
 enum { CS_MINK2_DIAMOND = 0, CS_MINK4_DIAMOND = 1, CS_DS4_SLAB = 2, CS_DS2_SLAB = 3,
        CS_MINK3_DIAMOND = 4 };
 
-/* Interval counters (all three give identical, exact results). */
+/* Interval counters (all four give identical, exact results). */
 enum {
-    CS_COUNT_BITSET = 0,   /* VALU: 32-bit AND + popcount over LDS-staged row words      */
+    CS_COUNT_BITSET = 0,   /* VALU: 32-bit AND + popcount over LDS-staged row words, on
+                              the related pairs only (Alg. "Optimized Interval Abundance
+                              Measurement"): a 128 x 128 tile's related pairs are packed
+                              into tasks of one row and up to four related columns; tiles
+                              where more than about half the pairs are related take the
+                              dense product of CS_COUNT_BITSET_DENSE instead              */
     CS_COUNT_MFMA = 1,     /* dense C.C on int8 MFMA (v_mfma_i32_32x32x32_i8), int32 acc  */
-    CS_COUNT_MFMA_FP4 = 2  /* dense C.C on fp4 MFMA (v_mfma_scale_f32_32x32x64_f8f6f4,
+    CS_COUNT_MFMA_FP4 = 2, /* dense C.C on fp4 MFMA (v_mfma_scale_f32_32x32x64_f8f6f4,
                               e2m1 operands 0 / 1.0, unit scales), f32 acc: exact because
                               every product is 0 or 1 and counts stay below 2^24; needs
                               n < 2^24 (CS_ERR_OVERFLOW otherwise)                        */
+    CS_COUNT_BITSET_DENSE = 3  /* VALU AND + popcount over every pair of each tile that
+                              holds a related pair (8 x 8 pairs per thread), unrelated
+                              pairs discarded at binning: the dense reference of the
+                              related-pair counter                                        */
 };
 
 /* Number of fp64 coordinate planes of a region (2, 4, 7, 3 or 3); -1 if unknown. */
@@ -132,7 +141,8 @@ size_t cs_histogram_workspace_bytes(int64_t n, int counter);
  * Interval abundances: hist[m] = N_m = number of pairs i < j with i ≺ j and exactly m
  * elements k with i ≺ k ≺ j, for m = 0 .. n-2 (the thesis's n_{m+1}).
  *   bits     device, the matrix from cs_causal_matrix (n rows, ld_words stride).
- *   counter  CS_COUNT_BITSET, CS_COUNT_MFMA or CS_COUNT_MFMA_FP4; identical results.
+ *   counter  CS_COUNT_BITSET, CS_COUNT_MFMA, CS_COUNT_MFMA_FP4 or CS_COUNT_BITSET_DENSE;
+ *            identical results.
  *   hist     device, n-1 uint64, overwritten (zeroed by the callee).
  *   workspace device, at least cs_histogram_workspace_bytes(n, counter) bytes.
  * The MFMA counters address a 256-row panel of the matrix with 32-bit offsets and

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libcausal.so")
 
 CS_MINK2_DIAMOND, CS_MINK4_DIAMOND, CS_DS4_SLAB, CS_DS2_SLAB, CS_MINK3_DIAMOND = 0, 1, 2, 3, 4
-CS_COUNT_BITSET, CS_COUNT_MFMA, CS_COUNT_MFMA_FP4 = 0, 1, 2
+CS_COUNT_BITSET, CS_COUNT_MFMA, CS_COUNT_MFMA_FP4, CS_COUNT_BITSET_DENSE = 0, 1, 2, 3
 REGION_DIM = {CS_MINK2_DIAMOND: 2, CS_MINK4_DIAMOND: 4, CS_DS4_SLAB: 4, CS_DS2_SLAB: 2,
               CS_MINK3_DIAMOND: 3}
 

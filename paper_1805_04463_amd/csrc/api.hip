@@ -18,6 +18,8 @@ constexpr int64_t kMaxChainPairs = 65535;
 
 inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+inline bool is_mfma(int counter) { return counter == CS_COUNT_MFMA || counter == CS_COUNT_MFMA_FP4; }
+
 cs_status check_n(int64_t n) {
   if (n < 2) return CS_ERR_INVALID_ARG;
   if (n >= kMaxN) return CS_ERR_OVERFLOW;
@@ -74,19 +76,19 @@ cs_status cs_causal_matrix(int region, const double* coords, int64_t n, uint64_t
 }
 
 size_t cs_histogram_workspace_bytes(int64_t n, int counter) {
-  if (check_n(n) != CS_OK || counter < CS_COUNT_BITSET || counter > CS_COUNT_MFMA_FP4) return 0;
+  if (check_n(n) != CS_OK || counter < CS_COUNT_BITSET || counter > CS_COUNT_BITSET_DENSE) return 0;
   return histogram_ws_bytes(n, counter);
 }
 
 cs_status cs_interval_histogram(const uint64_t* bits, int64_t n, int64_t ld_words_, int counter,
                                 uint64_t* hist, void* workspace, size_t workspace_bytes,
                                 void* stream) {
-  if (counter < CS_COUNT_BITSET || counter > CS_COUNT_MFMA_FP4) return CS_ERR_UNSUPPORTED;
+  if (counter < CS_COUNT_BITSET || counter > CS_COUNT_BITSET_DENSE) return CS_ERR_UNSUPPORTED;
   cs_status s = check_n(n);
   if (s != CS_OK) return s;
   if (!bits || !hist || !workspace || ld_words_ < ld_words(n)) return CS_ERR_INVALID_ARG;
   if (counter == CS_COUNT_MFMA_FP4 && n >= (int64_t)1 << 24) return CS_ERR_OVERFLOW;
-  if (counter != CS_COUNT_BITSET && ld_words_ > kMaxMfmaLd) return CS_ERR_OVERFLOW;
+  if (is_mfma(counter) && ld_words_ > kMaxMfmaLd) return CS_ERR_OVERFLOW;
   if (workspace_bytes < histogram_ws_bytes(n, counter)) return CS_ERR_WORKSPACE;
   return launch_histogram(bits, n, ld_words_, counter, hist, workspace, as_stream(stream));
 }

@@ -138,11 +138,16 @@ struct Stage {
       v[q] = x;
     }
   }
+  // SWZ: the XOR-swizzled layout of lds_pos (dense tiles); else row r at r * kStageWords,
+  // its halves at +0 and +4 words (related-pair tiles, whose reads take the second half
+  // through the instruction's immediate offset).
+  template <bool SWZ = true>
   __device__ inline void store(uint32_t* lds) const {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int c = threadIdx.x + q * kThreads;
-      *(uint4*)(lds + lds_pos(c >> 1, c & 1)) = v[q];
+      const int pos = SWZ ? lds_pos(c >> 1, c & 1) : (c >> 1) * kStageWords + (c & 1) * 4;
+      *(uint4*)(lds + pos) = v[q];
     }
   }
 };
@@ -776,6 +781,176 @@ __device__ inline bool bitset_tile(const TileArgs& ta, uint32_t* As, uint32_t* B
 }
 
 // ===========================================================================
+// Related-pair tile (bitset counter, Alg. "Optimized Interval Abundance Measurement":
+// only related pairs are counted).  Sprinkled orders are sparse near the diagonal and
+// dense far from it: in a 3+1 diamond three quarters of the 128 x 128 tiles relate fewer
+// than one pair in ten, while the tiles with half or more of their pairs related hold
+// over half of the related-pair work.  So each tile first collects its related pairs and
+// then takes one of two paths:
+//   - few related pairs (at most `pair_max` tasks): the pairs are packed into tasks of
+//     up to four related columns of one row; each thread holds up to kPairSlots tasks in
+//     registers and, per staged K chunk, ANDs the task row's words with each of its
+//     columns' words and accumulates v_bcnt.  One A read serves four columns.
+//   - many related pairs: the dense 8 x 8 register-blocked product of bitset_tile.
+// Tasks come from a workgroup scan of the rows' task counts (ceil(related / 4)); a
+// task's columns are the row's related columns number 4k .. 4k+3 in its 128-bit slice.
+// Unused columns of a task read a zero row kept after the B stage.
+// ===========================================================================
+constexpr int kPairGroup = 4;                        // related columns per task
+constexpr int kPairSlots = 9;                        // tasks per thread
+constexpr int kPairTaskMax = kPairSlots * kThreads;  // tasks per tile on the pair path
+constexpr int kZeroRow = kBitsetTile;                // B-stage row that stays zero
+
+// Exclusive prefix sum of v over the workgroup in thread order; *total gets the sum.
+// wsum: kThreads / 64 words of LDS.
+__device__ inline int block_exclusive_scan(int v, int* wsum, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    const int sw = wsum[w];
+    off += w < wave ? sw : 0;
+    tot += sw;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
+}
+
+struct PairLds {
+  uint32_t rowmask[kBitsetTile * 4];  // related columns of each tile row (j > i only)
+  uint16_t task[kPairTaskMax];        // (row << 8) | number of the task's first column
+  int wsum[kThreads / 64];
+};
+
+// Returns 0 when no pair of the tile is related (nothing done), 1 after the pair path,
+// 2 when the tile has too many related pairs for it (nothing done: the caller takes the
+// dense path).
+template <int HB>
+__device__ inline int pair_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs, PairLds& P,
+                                uint32_t* lds_hist, uint32_t& tmax, int pair_max) {
+  constexpr int BM = kBitsetTile;
+  const int64_t n = ta.n, I0 = ta.I0, J0 = ta.J0, nbins = n - 1;
+  const int tid = threadIdx.x, wave = tid >> 6;
+
+  // Related columns: thread (r, h) = (tid / 2, tid % 2) takes the 64 columns
+  // [J0 + 64h, J0 + 64h + 64) of row I0 + r; on a diagonal tile only j > i.
+  int ntask;
+  {
+    const int r = tid >> 1, h = tid & 1;
+    const int64_t i = I0 + r;
+    uint64_t m = 0;
+    if (i < n) m = *(const uint64_t*)(ta.S32 + i * ta.ld32 + (J0 >> 5) + 2 * h);
+    if (I0 == J0) {
+      const int lo = r + 1 - 64 * h;  // keep column bits b >= lo
+      m = lo >= 64 ? 0ull : (lo <= 0 ? m : m & (~0ull << lo));
+    }
+    P.rowmask[4 * r + 2 * h] = (uint32_t)m;
+    P.rowmask[4 * r + 2 * h + 1] = (uint32_t)(m >> 32);
+    const int c = __popcll(m);
+    const int row = c + __shfl_xor(c, 1);
+    const int nt = h == 0 ? (row + kPairGroup - 1) / kPairGroup : 0;
+    const int off = block_exclusive_scan(nt, P.wsum, &ntask);
+    if (ntask == 0) return 0;
+    if (ntask > pair_max) return 2;
+    for (int k = 0; k < nt; ++k) P.task[off + k] = (uint16_t)((r << 8) | (kPairGroup * k));
+  }
+  __syncthreads();
+
+  // Tasks q * kThreads + tid -> byte offsets of the task row in the A stage and of its
+  // columns' rows in the B stage (the zero row where a task has fewer columns).
+  constexpr int kRowBytes = kStageWords * 4;
+  constexpr uint32_t kZeroOff = kZeroRow * kRowBytes;
+  uint32_t aoff[kPairSlots], boff[kPairSlots][kPairGroup], acc[kPairSlots][kPairGroup];
+#pragma unroll
+  for (int q = 0; q < kPairSlots; ++q) {
+    const int t = q * kThreads + tid;
+    aoff[q] = 0;
+#pragma unroll
+    for (int g = 0; g < kPairGroup; ++g) {
+      boff[q][g] = kZeroOff;
+      acc[q][g] = 0;
+    }
+    if (t < ntask) {
+      const uint32_t e = P.task[t];
+      const int r = (int)(e >> 8);
+      int skip = (int)(e & 255u);
+      aoff[q] = (uint32_t)(r * kRowBytes);
+      // Walk the row's 128-bit slice: skip `skip` related columns, take the next four.
+      int w = 0;
+      uint32_t x = P.rowmask[4 * r];
+      while (w < 3 && skip >= __popc(x)) {
+        skip -= __popc(x);
+        x = P.rowmask[4 * r + (++w)];
+      }
+      for (; skip > 0; --skip) x &= x - 1u;
+#pragma unroll
+      for (int g = 0; g < kPairGroup; ++g) {
+        while (x == 0u && w < 3) x = P.rowmask[4 * r + (++w)];
+        if (x != 0u) {
+          boff[q][g] = (uint32_t)((32 * w + __ffs(x) - 1) * kRowBytes);
+          x &= x - 1u;
+        }
+      }
+    }
+  }
+
+  const int64_t kbeg = I0;
+  const int64_t kend = (J0 + BM < n ? J0 + BM : n);
+  const int64_t nst = ceil_div(kend - kbeg, kStageBits);
+  const int64_t row_bits = ta.ld32 * 32;
+  Stage<BM> sa, sb;
+  sa.init(ta.S32, ta.ld32, I0, n, kbeg);
+  sb.init(ta.S32, ta.ld32, J0, n, kbeg);
+  sa.fetch(0, kbeg, row_bits, I0, kbeg < I0 + BM, true);
+  sb.fetch(0, kbeg, row_bits, J0, kbeg + kStageBits > J0, false);
+  const char* Ab = (const char*)As;
+  const char* Bb = (const char*)Bs;
+  for (int64_t s = 0; s < nst; ++s) {
+    __syncthreads();
+    sa.store<false>(As);
+    sb.store<false>(Bs);
+    __syncthreads();
+    if (s + 1 < nst) {
+      const int64_t kb = kbeg + (s + 1) * kStageBits;
+      sa.fetch(s + 1, kb, row_bits, I0, kb < I0 + BM, true);
+      sb.fetch(s + 1, kb, row_bits, J0, kb + kStageBits > J0, false);
+    }
+#pragma unroll
+    for (int q = 0; q < kPairSlots; ++q) {
+      if (q * kThreads + wave * 64 < ntask) {  // wave-uniform: a task in this slot
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const uint4 a = *(const uint4*)(Ab + aoff[q] + 16 * h);
+#pragma unroll
+          for (int g = 0; g < kPairGroup; ++g) {
+            const uint4 b = *(const uint4*)(Bb + boff[q][g] + 16 * h);
+            acc[q][g] += __popc(a.x & b.x);
+            acc[q][g] += __popc(a.y & b.y);
+            acc[q][g] += __popc(a.z & b.z);
+            acc[q][g] += __popc(a.w & b.w);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kPairSlots; ++q)
+#pragma unroll
+    for (int g = 0; g < kPairGroup; ++g)
+      if (boff[q][g] != kZeroOff) bin_add<HB>(lds_hist, ta.hist, acc[q][g], nbins, tmax);
+  return 1;
+}
+
+// ===========================================================================
 // XCD-aware tile schedule for the MFMA counters.
 //
 // The MI355X's 256 CUs sit in 8 XCDs, each with its own L2.  Tiles that share a row
@@ -882,7 +1057,8 @@ struct MfmaLds {
 template <int HB>
 struct BitsetLds {
   uint32_t As[kBitsetTile * kStageWords] __attribute__((aligned(16)));
-  uint32_t Bs[kBitsetTile * kStageWords] __attribute__((aligned(16)));
+  uint32_t Bs[(kBitsetTile + 1) * kStageWords] __attribute__((aligned(16)));  // + zero row
+  PairLds pairs;
   uint32_t hist[HB];
   uint32_t maxbin;
   int slot;
@@ -944,12 +1120,14 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
 __global__ __launch_bounds__(kThreads, 2) void k_count_bitset(const uint64_t* __restrict__ S,
                                                               int64_t n, int64_t ld,
                                                               unsigned long long* __restrict__ hist,
-                                                              unsigned int* __restrict__ counter) {
+                                                              unsigned int* __restrict__ counter,
+                                                              int pair_max) {
   constexpr int BM = kBitsetTile, HB = kBinsSingle;
   __shared__ BitsetLds<HB> L;
   const int64_t T = ceil_div(n, BM);
   const int64_t ntiles = T * (T + 1) / 2;
   for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
+  if (threadIdx.x < kStageWords) L.Bs[kZeroRow * kStageWords + threadIdx.x] = 0;
   uint32_t tmax = 0;
   int64_t pairs_in_lds = 0;
   TileArgs ta{(const uint32_t*)S, 2 * ld, n, 0, 0, hist};
@@ -964,7 +1142,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_count_bitset(const uint64_t* __
     }
     ta.I0 = I * BM;
     ta.J0 = J * BM;
-    if (bitset_tile<HB>(ta, L.As, L.Bs, L.hist, tmax)) pairs_in_lds += (int64_t)BM * BM;
+    const int path = pair_tile<HB>(ta, L.As, L.Bs, L.pairs, L.hist, tmax, pair_max);
+    if (path == 2) bitset_tile<HB>(ta, L.As, L.Bs, L.hist, tmax);
+    if (path) pairs_in_lds += (int64_t)BM * BM;
   }
   flush_hist<HB>(L.hist, hist, n - 1, tmax, &L.maxbin);
 }
@@ -1094,7 +1274,8 @@ cs_status launch_histogram(const uint64_t* bits, int64_t n, int64_t ld, int coun
       const int64_t T = ceil_div(n, 128);
       const unsigned grid = (unsigned)std::min<int64_t>(T * (T + 1) / 2, 2 * device_cu_count());
       hipLaunchKernelGGL(k_count_bitset, dim3(grid), dim3(kThreads), 0, st, bits, n, ld,
-                         (unsigned long long*)hist, ctr);
+                         (unsigned long long*)hist, ctr,
+                         counter == CS_COUNT_BITSET_DENSE ? -1 : kPairTaskMax);
       CS_LAUNCH_CHECK();
       return CS_OK;
     }

@@ -48,6 +48,7 @@ def test_sizes_and_strings(L):
     assert L.cs_histogram_workspace_bytes(1000, 1) > 0
     assert L.cs_histogram_workspace_bytes(1000, 2) > 0
     assert L.cs_histogram_workspace_bytes(1000, 5) == 0
+    assert L.cs_histogram_workspace_bytes(1000, 3) > 0
 
 
 def test_argument_errors_need_no_device(L):
@@ -55,7 +56,7 @@ def test_argument_errors_need_no_device(L):
     null = ctypes.c_void_p(0)
     # unknown region / counter / dimension
     assert L.cs_sprinkle(5, 1.2, 1, 100, p, p, 1 << 20, null) == 2
-    assert L.cs_interval_histogram(p, 100, 8, 3, p, p, 256, null) == 2
+    assert L.cs_interval_histogram(p, 100, 8, 4, p, p, 256, null) == 2
     assert L.cs_action(p, 100, 5, 0.0, p, null) == 2
     # n < 2, n >= 2^31
     assert L.cs_causal_matrix(0, p, 1, p, 8, null) == 1

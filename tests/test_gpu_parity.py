@@ -127,7 +127,7 @@ COUNT_CASES = [(W.MINK2_DIAMOND, n) for n in (2, 3, 5, 64, 129, 255, 256, 257, 7
               [(W.DS4_SLAB, n) for n in (3, 600, 2500, 4100)]
 
 
-@pytest.mark.parametrize("counter", [0, 1, 2], ids=["bitset", "mfma", "mfma_fp4"])
+@pytest.mark.parametrize("counter", [0, 1, 2, 3], ids=["bitset", "mfma", "mfma_fp4", "bitset_dense"])
 @pytest.mark.parametrize("region,n", COUNT_CASES)
 def test_interval_histogram_bit_exact(cs, orc, counter, region, n):
     coords = orc.sprinkle(region, n, seed=900 + n)
@@ -150,7 +150,7 @@ def test_action_every_bin_filled(cs, orc):
             assert abs(got - want) <= 1e-12 * abs(want), (dim, eps, got, want)
 
 
-@pytest.mark.parametrize("counter", [0, 1, 2], ids=["bitset", "mfma", "mfma_fp4"])
+@pytest.mark.parametrize("counter", [0, 1, 2, 3], ids=["bitset", "mfma", "mfma_fp4", "bitset_dense"])
 @pytest.mark.parametrize("n", [2, 65, 300, 4500])
 def test_chain_and_antichain_counts(cs, orc, counter, n):
     k = np.arange(1, n + 1, dtype=np.float64) / (n + 1)
@@ -169,7 +169,9 @@ def test_counters_deterministic(cs, orc):
     b = host_u64(cs.cs_interval_histogram(bits, n, 1)).copy()
     c = host_u64(cs.cs_interval_histogram(bits, n, 0)).copy()
     d = host_u64(cs.cs_interval_histogram(bits, n, 2)).copy()
+    e = host_u64(cs.cs_interval_histogram(bits, n, 3)).copy()
     assert np.array_equal(a, b) and np.array_equal(a, c) and np.array_equal(a, d)
+    assert np.array_equal(a, e)
 
 
 @pytest.mark.parametrize("dim", [2, 4])
@@ -196,7 +198,7 @@ def test_action_synthetic_histograms(cs, orc):
                 assert abs(got - want) <= 1e-12 * abs(want), (n, dim, eps, got, want)
 
 
-@pytest.mark.parametrize("counter", [0, 1, 2], ids=["bitset", "mfma", "mfma_fp4"])
+@pytest.mark.parametrize("counter", [0, 1, 2, 3], ids=["bitset", "mfma", "mfma_fp4", "bitset_dense"])
 def test_pipeline_mink2_n1024(cs, orc, counter):
     """Whole path from the seed on the GPU against the whole path on the CPU."""
     cfg = W.WORKLOADS["mink2_n1024"]

@@ -71,16 +71,17 @@ def test_constant_field_gives_the_action(cs, region, dim):
 
 def test_n131072_sampled_elements(cs, orc):
     """At the bench size (3+1 diamond, N = 131072, fp4 tiles), B phi of sampled elements
-    against the oracle's sums for those elements, within the summation-order bound."""
+    against the oracle's sums for those elements, within the summation-order bound; the
+    device matrix is built from the oracle's coordinates, the oracle uses its own matrix."""
     cfg = W.WORKLOADS["mink4_n131072"]
     n, seed, ell = cfg["n"], cfg["seed"], 0.01
-    c = cs.cs_sprinkle(W.MINK4_DIAMOND, n, seed)
-    b = cs.cs_causal_matrix(W.MINK4_DIAMOND, c)
+    coords = orc.sprinkle(W.MINK4_DIAMOND, n, seed)
+    b = cs.cs_causal_matrix(W.MINK4_DIAMOND, torch.from_numpy(coords).cuda())
     phi = np.random.default_rng(73).normal(size=n)
     got = cs.cs_dalembertian(b, n, 4, ell, torch.from_numpy(phi).cuda()).cpu().numpy()
     torch.cuda.synchronize()
-    bits = b.cpu().numpy().view(np.uint64)
     del b
+    bits = orc.causal_matrix(W.MINK4_DIAMOND, coords)
     rng = np.random.default_rng(74)
     js = np.unique(np.concatenate([[0, 1, n // 2, n - 2, n - 1], rng.integers(0, n, 11)]))
     want, terms, mag = orc.dalembertian_cols(bits, n, 4, ell, phi, js)

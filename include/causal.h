@@ -153,6 +153,19 @@ cs_status cs_interval_histogram(const uint64_t *bits, int64_t n, int64_t ld_word
                                 uint64_t *hist, void *workspace, size_t workspace_bytes,
                                 void *stream);
 
+/*
+ * cs_interval_histogram without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, limits and results as cs_interval_histogram; the counters'
+ * scratch memory is a static device array of the library (16 KiB, one copy per GPU, held
+ * until the process ends), so this call allocates nothing.  A counter whose workspace
+ * (cs_histogram_workspace_bytes) exceeds that array gives CS_ERR_WORKSPACE.  Every call on
+ * one GPU shares the array: calls on one GPU that overlap in time (on different streams,
+ * or from host threads without ordering) race and must be serialised by the caller.
+ */
+cs_status cs_interval_histogram_noalloc(const uint64_t *bits, int64_t n, int64_t ld_words,
+                                        int counter, uint64_t *hist, void *stream);
+
 /* Device workspace needed by cs_dalembertian, in bytes (0 for a bad n or counter). */
 size_t cs_dalembertian_workspace_bytes(int64_t n, int counter);
 

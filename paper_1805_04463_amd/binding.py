@@ -28,7 +28,7 @@ SYMBOLS = [
     "cs_batch_hist_offset", "cs_batch_run", "cs_batch_free", "cs_batch_graph_create",
     "cs_batch_graph_launch", "cs_batch_graph_destroy", "cs_autotune", "cs_measure_mfma_peak",
     "cs_dalembertian_workspace_bytes", "cs_dalembertian", "cs_longest_chain_workspace_bytes",
-    "cs_longest_chain", "cs_degrees",
+    "cs_longest_chain", "cs_degrees", "cs_interval_histogram_noalloc",
 ]
 
 
@@ -57,6 +57,7 @@ def lib():
             "cs_causal_matrix": (c_int, [c_int, p, i64, p, i64, p]),
             "cs_histogram_workspace_bytes": (sz, [i64, c_int]),
             "cs_interval_histogram": (c_int, [p, i64, i64, c_int, p, p, sz, p]),
+            "cs_interval_histogram_noalloc": (c_int, [p, i64, i64, c_int, p, p]),
             "cs_action": (c_int, [p, i64, c_int, dbl, p, p]),
             "cs_dalembertian_workspace_bytes": (sz, [i64, c_int]),
             "cs_dalembertian": (c_int, [p, i64, i64, c_int, dbl, c_int, p, p, p, sz, p]),
@@ -234,6 +235,19 @@ def cs_interval_histogram(bits: torch.Tensor, n: int, counter: int = CS_COUNT_MF
                                        _stream(stream)), "cs_interval_histogram")
     hist._cs_keepalive = ws
     return hist
+
+
+def cs_interval_histogram_noalloc(bits: torch.Tensor, n: int, out: torch.Tensor,
+                                  counter: int = CS_COUNT_MFMA, stream=None) -> torch.Tensor:
+    """cs_interval_histogram into the caller's `out` (n-1 int64), with the library's static
+    scratch instead of a workspace: no device memory is allocated."""
+    n = _int(n, "n")
+    pbits, ld = _bits(bits, n)
+    ph = _need(out, "out", _WORDS, numel=n - 1)
+    _on_device(bits, out)
+    _check(lib().cs_interval_histogram_noalloc(pbits, n, ld, counter, ph, _stream(stream)),
+           "cs_interval_histogram_noalloc")
+    return out
 
 
 def cs_dalembertian(bits: torch.Tensor, n: int, dim: int, ell: float, phi: torch.Tensor,

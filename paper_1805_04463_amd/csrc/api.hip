@@ -93,6 +93,21 @@ cs_status cs_interval_histogram(const uint64_t* bits, int64_t n, int64_t ld_word
   return launch_histogram(bits, n, ld_words_, counter, hist, workspace, as_stream(stream));
 }
 
+cs_status cs_interval_histogram_noalloc(const uint64_t* bits, int64_t n, int64_t ld_words_,
+                                        int counter, uint64_t* hist, void* stream) {
+  if (counter < CS_COUNT_BITSET || counter > CS_COUNT_BITSET_DENSE) return CS_ERR_UNSUPPORTED;
+  cs_status s = check_n(n);
+  if (s != CS_OK) return s;
+  if (!bits || !hist || ld_words_ < ld_words(n)) return CS_ERR_INVALID_ARG;
+  if (counter == CS_COUNT_MFMA_FP4 && n >= (int64_t)1 << 24) return CS_ERR_OVERFLOW;
+  if (is_mfma(counter) && ld_words_ > kMaxMfmaLd) return CS_ERR_OVERFLOW;
+  if (histogram_ws_bytes(n, counter) > kScratchBytes) return CS_ERR_WORKSPACE;
+  void* ws = nullptr;
+  s = scratch_for_current_device(&ws);
+  if (s != CS_OK) return s;
+  return launch_histogram(bits, n, ld_words_, counter, hist, ws, as_stream(stream));
+}
+
 size_t cs_dalembertian_workspace_bytes(int64_t n, int counter) {
   if (check_n(n) != CS_OK || (counter != CS_COUNT_MFMA && counter != CS_COUNT_MFMA_FP4)) return 0;
   return field_ws_bytes(n, counter);

@@ -121,6 +121,11 @@ cs_status launch_degrees(const uint64_t* bits, int64_t n, int64_t ld, int64_t* i
                          int64_t* outdeg, hipStream_t st);
 int device_cu_count();
 
+// Allocation-free entry points: bytes of the per-device static scratch array, and its
+// device address on the current device (looked up once per device).
+constexpr size_t kScratchBytes = 16384;
+cs_status scratch_for_current_device(void** out);
+
 // Ensemble pieces (1+1 diamonds).
 cs_status launch_sprinkle_batch(const uint64_t* seeds, const BatchInst* inst, int64_t count,
                                 double* coords, hipStream_t st);

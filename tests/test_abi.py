@@ -108,6 +108,15 @@ def test_argument_errors_need_no_device(L):
     # MFMA counters: 256-row panels must stay below 1 GiB (ld_words <= 2^19)
     assert L.cs_interval_histogram(p, 1000, (1 << 19) + 1, 1, p, p, 256, null) == 4
     assert L.cs_interval_histogram(p, 1000, (1 << 19) + 1, 2, p, p, 256, null) == 4
+    # allocation-free variant: the same checks, before its scratch array is looked up
+    assert L.cs_interval_histogram_noalloc(p, 100, 8, 4, p, null) == 2
+    assert L.cs_interval_histogram_noalloc(p, 1, 8, 1, p, null) == 1
+    assert L.cs_interval_histogram_noalloc(p, 1 << 31, 1 << 25, 1, p, null) == 4
+    assert L.cs_interval_histogram_noalloc(null, 100, 8, 1, p, null) == 1
+    assert L.cs_interval_histogram_noalloc(p, 100, 8, 1, null, null) == 1
+    assert L.cs_interval_histogram_noalloc(p, 1000, 8, 1, p, null) == 1
+    assert L.cs_interval_histogram_noalloc(p, 1 << 24, 1 << 18, 2, p, null) == 4
+    assert L.cs_interval_histogram_noalloc(p, 1000, (1 << 19) + 1, 1, p, null) == 4
 
 
 def test_batch_plan_argument_errors_need_no_device(L):

@@ -73,29 +73,9 @@ def test_mink3_dalembertian(cs, orc):
 
 
 def test_mink3_n131072(cs, orc):
-    """The 2+1 bench leg's size: coordinates bit-exact; matrix rows sampled against the
-    oracle's rows; N_n by the exact invariants sum N_n = R and sum n N_n = sum indeg *
-    outdeg (from the matrix), the int8 and fp4 counters identical; the actions of the
-    device histogram against the oracle's actions of the same histogram."""
-    from test_gpu_fullsize import degree_moments
-    n, seed = 131072, 5
-    c = cs.cs_sprinkle(W.MINK3_DIAMOND, n, seed)
-    coords = c.cpu().numpy()
-    assert np.array_equal(coords, orc.sprinkle(W.MINK3_DIAMOND, n, seed))
-    b = cs.cs_causal_matrix(W.MINK3_DIAMOND, c)
-    got = host_u64(b)
-    rng = np.random.default_rng(75)
-    rows = np.unique(np.concatenate([np.arange(32), rng.integers(0, n, 160), np.arange(n - 32, n)]))
-    assert np.array_equal(got[rows], orc.causal_rows(W.MINK3_DIAMOND, coords, rows))
-    rel, c3 = degree_moments(got, n)
-    del got
-    hf = host_u64(cs.cs_interval_histogram(b, n, cs.CS_COUNT_MFMA_FP4)).copy()
-    hm = host_u64(cs.cs_interval_histogram(b, n, cs.CS_COUNT_MFMA)).copy()
-    assert np.array_equal(hf, hm)
-    assert int(hf.sum()) == rel
-    assert int((np.arange(n - 1, dtype=np.uint64) * hf).sum()) == c3
-    h = torch.from_numpy(hf.view(np.int64)).cuda()
-    for eps in (0.0, 0.05, 0.1, 0.2):
-        want = orc.action(hf, n, 3, eps)[0]
-        got_a = cs.cs_action(h, n, 3, eps).item()
-        assert abs(got_a - want) <= 1e-12 * max(abs(want), 1.0), (eps, got_a, want)
+    """The 2+1 bench leg's size: coordinates and the whole matrix bit-exact against the
+    oracle's; N_n of the int8, fp4 and bitset counters bin by bin against the stored oracle
+    abundances; actions against the oracle's actions of those abundances."""
+    from test_gpu_fullsize import fullsize_parity
+    fullsize_parity(cs, orc, "mink3_n131072",
+                    (cs.CS_COUNT_MFMA_FP4, cs.CS_COUNT_MFMA, cs.CS_COUNT_BITSET))

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import os
 import tempfile
+import time
 
 import numpy as np
 
@@ -22,20 +23,33 @@ def run_batch(cs, torch, dev, stream, reps: int = 5):
     count = len(sizes)
 
     tune = os.path.join(tempfile.gettempdir(), "cs_tune_gfx950.json")
+    if os.path.exists(tune):
+        os.remove(tune)
+    t0 = time.perf_counter()
     cs.cs_autotune(tune, stream=stream)
     torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
     import json
-    tuned = json.load(open(tune))
+    tuned = {}
+    for e in json.load(open(tune))["entries"]:
+        tuned.setdefault(e["counter"], []).append(
+            {"n": [e["n_lo"], e["n_hi"]], "tile": e["tile"], "per_cu": e["per_cu"],
+             **({"pair_max": e["pair_max"]} if e["counter"] == "bitset" else {}),
+             "probe_ms": e["ms"], "probe": [e["probe_instances"], e["probe_n"]]})
 
     def ev():
         return torch.cuda.Event(enable_timing=True)
 
     out = {"instances": count, "n_range": [int(sizes.min()), int(sizes.max())],
-           "tile256_min_n": tuned["tile256_min_n"]}
+           "autotune": {"seconds": tune_s, "choices": tuned}}
     results = {}
-    for name, counter in (("mfma", cs.CS_COUNT_MFMA), ("mfma_fp4", cs.CS_COUNT_MFMA_FP4),
-                          ("bitset", cs.CS_COUNT_BITSET)):
-        plan = cs.BatchPlan(sizes, counter=counter, eps=eps, tune_cache=tune)
+    # each counter with the tuned tiles; the fp4 counter also with the library's default
+    # tiles (no cache), to show what the tuner changes
+    for name, counter, cache in (("mfma", cs.CS_COUNT_MFMA, tune),
+                                 ("mfma_fp4", cs.CS_COUNT_MFMA_FP4, tune),
+                                 ("bitset", cs.CS_COUNT_BITSET, tune),
+                                 ("mfma_fp4_default_tiles", cs.CS_COUNT_MFMA_FP4, None)):
+        plan = cs.BatchPlan(sizes, counter=counter, eps=eps, tune_cache=cache)
         s = torch.from_numpy(seeds.view(np.int64)).to(dev)
         hist = torch.empty(plan.hist_len, dtype=torch.int64, device=dev)
         acts = torch.empty(count * len(eps), dtype=torch.float64, device=dev)

@@ -296,15 +296,28 @@ cs_status cs_batch_graph_launch(void *graph_exec, void *stream);
 cs_status cs_batch_graph_destroy(void *graph_exec);
 
 /*
- * Tile autotuner (project-written): on the current device, times the MFMA counter with
- * 128x128 and 256x256 output tiles on ensembles of 16 diamonds at each size of a fixed
- * ladder (512 .. 8192 points, best of three launches each, HIP events on `stream`) and
- * writes JSON {"tile256_min_n": N, "ms": [...]} to cache_path: the smallest size from
- * which the 256 tiles are faster at every larger size.  It allocates and frees its own
- * device memory and synchronises `stream`.  cs_batch_plan reads `tune_cache` (may be
- * NULL: then instances with n >= 4096 use 256 tiles).
+ * Tile autotuner (project-written) of the ensemble counters.  Instance sizes fall in four
+ * buckets, [2, 1023], [1024, 2047], [2048, 4095] and [4096, 8192].  For each requested
+ * counter and bucket it times, on the current device, every tile configuration of the
+ * counter on an ensemble of diamonds of one size in the bucket (768, 1536, 3072 or 6144
+ * points; enough of them that their row panels of 128-row tiles number eight per compute
+ * unit, at least 16; the counting launches only, best of three, HIP events on `stream`):
+ *   CS_COUNT_MFMA, CS_COUNT_MFMA_FP4: 128x128 output tiles with two or with one
+ *       persistent workgroup per compute unit, 256x256 tiles with one;
+ *   CS_COUNT_BITSET: related-pair tiles with at most 2304 or 1152 tasks (denser tiles
+ *       take the dense product), two workgroups per CU; the same with one; and the dense
+ *       product on every tile.
+ *   n_bucket   0: every bucket; else the bucket holding this size (2 .. 8192).
+ *   counter    CS_COUNT_BITSET, CS_COUNT_MFMA, CS_COUNT_MFMA_FP4, or -1 for all three.
+ * The fastest configuration of each (counter, bucket) is stored in the JSON file
+ * cache_path (one entry per line, keeping the entries of an existing file that were not
+ * re-tuned).  cs_batch_plan reads its own counter's entries from `tune_cache` (may be
+ * NULL); without an entry it uses 128 tiles below 4096 points and 256 tiles from 4096
+ * (MFMA), related-pair tiles with at most 2304 tasks (bitset).  The tuner allocates and
+ * frees its own device memory and synchronises `stream`.  Every configuration gives
+ * identical, exact histograms.
  */
-cs_status cs_autotune(const char *cache_path, void *stream);
+cs_status cs_autotune(const char *cache_path, int64_t n_bucket, int counter, void *stream);
 
 /*
  * Measurement utility (not part of the pipeline): the int8 (counter = CS_COUNT_MFMA) or fp4

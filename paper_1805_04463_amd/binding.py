@@ -73,7 +73,7 @@ def lib():
             "cs_batch_graph_create": (c_int, [p, p, p, p, p, sz, ctypes.POINTER(p)]),
             "cs_batch_graph_launch": (c_int, [p, p]),
             "cs_batch_graph_destroy": (c_int, [p]),
-            "cs_autotune": (c_int, [ctypes.c_char_p, p]),
+            "cs_autotune": (c_int, [ctypes.c_char_p, i64, c_int, p]),
             "cs_measure_mfma_peak": (c_int, [c_int, ctypes.POINTER(dbl), p]),
         }
         for name, (res, args) in sig.items():
@@ -387,8 +387,11 @@ class BatchGraph:
             pass
 
 
-def cs_autotune(cache_path: str, stream=None):
-    _check(lib().cs_autotune(cache_path.encode(), _stream(stream)), "cs_autotune")
+def cs_autotune(cache_path: str, n_bucket: int = 0, counter: int = -1, stream=None):
+    """Tune the ensemble counters' tiles per size bucket (n_bucket 0: all buckets; counter
+    -1: all three counters) and write the choices to the JSON file cache_path."""
+    _check(lib().cs_autotune(cache_path.encode(), _int(n_bucket, "n_bucket"), int(counter),
+                             _stream(stream)), "cs_autotune")
 
 
 def cs_measure_mfma_peak(counter: int, stream=None) -> float:

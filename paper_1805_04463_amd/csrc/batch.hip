@@ -7,13 +7,18 @@
 // the counters' work lists (one item per row panel I of output tiles, i.e. all tiles
 // (I, J >= I) of an instance, so a workgroup keeps one instance's histogram in LDS for
 // a whole panel), sorted by cost across all instances so the persistent counter
-// balances instances of very different sizes.  These tables live in device memory owned by the plan, uploaded
-// once at plan time, so a run only enqueues kernels: fill, sprinkle, build, count
-// (one persistent launch per tile shape in use), action.
+// balances instances of very different sizes.  These tables live in device memory owned
+// by the plan, uploaded once at plan time, so a run only enqueues kernels: fill,
+// sprinkle, build, count (one persistent launch per tile configuration in use), action.
 //
-// Tile shape: the MFMA counter has 128x128 and 256x256 output tiles.  Instances with
-// n >= tile256_min_n use the larger one.  cs_autotune measures the crossover on the
-// device and stores it as JSON; cs_batch_plan reads that file when given its path.
+// Tile configuration per instance: the counter's configuration for the instance's size
+// bucket.  The candidates are, for the MFMA counters, 128x128 tiles with one or two
+// workgroups per CU and 256x256 tiles (one per CU); for the bitset counter, the dense
+// product on every tile or the related-pair tiles with two thresholds, two workgroups
+// per CU, and the related-pair tiles with one.  cs_autotune times every candidate on
+// the device per (counter, bucket) and stores the fastest in a JSON cache, one entry per
+// line; cs_batch_plan reads its counter's entries from that file when given its path
+// and falls back to fixed defaults for the rest.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -25,6 +30,135 @@
 
 using namespace cs;
 
+namespace {
+
+constexpr int kMaxSlots = 8;  // distinct tile configurations in one plan
+
+// Size buckets of the tuner: [lo, hi] and the size timed for each.
+constexpr int kBuckets = 4;
+constexpr int64_t kBucketLo[kBuckets] = {2, 1024, 2048, 4096};
+constexpr int64_t kBucketHi[kBuckets] = {1023, 2047, 4095, kBatchMaxN};
+constexpr int64_t kBucketProbe[kBuckets] = {768, 1536, 3072, 6144};
+
+int bucket_of(int64_t n) {
+  for (int b = 0; b < kBuckets; ++b)
+    if (n <= kBucketHi[b]) return b;
+  return kBuckets - 1;
+}
+
+// Counter slots of the cache: 0 bitset, 1 int8 MFMA, 2 fp4 MFMA.
+constexpr const char* kCounterName[3] = {"bitset", "mfma", "mfma_fp4"};
+
+bool same_tile(const BatchTile& a, const BatchTile& b) {
+  return a.mode == b.mode && a.per_cu == b.per_cu && a.pair_max == b.pair_max;
+}
+
+// Candidates the tuner times per counter family.
+const BatchTile kMfmaCandidates[] = {{2, 2, 0}, {2, 1, 0}, {4, 1, 0}};
+const BatchTile kBitsetCandidates[] = {{0, 2, -1}, {0, 2, 1152}, {0, 2, 2304}, {0, 1, 2304}};
+
+// Defaults without a cache entry: MFMA 128 tiles, two per CU, below 4096 points and 256
+// tiles from there; the bitset counter on related-pair tiles with the largest task list.
+BatchTile default_tile(int counter, int64_t n) {
+  if (counter == CS_COUNT_BITSET) return {0, 2, 2304};
+  return n >= 4096 ? BatchTile{4, 1, 0} : BatchTile{2, 2, 0};
+}
+
+struct TuneTable {
+  bool have[3][kBuckets] = {};
+  BatchTile cfg[3][kBuckets] = {};
+  double ms[3][kBuckets] = {};
+  int64_t reps[3][kBuckets] = {};  // instances of the probe ensemble
+};
+
+int counter_slot(int counter) {
+  return counter == CS_COUNT_BITSET ? 0 : (counter == CS_COUNT_MFMA ? 1 : 2);
+}
+
+long long field_ll(const char* entry, const char* end, const char* key, bool* ok) {
+  const char* k = strstr(entry, key);
+  if (!k || k > end) {
+    *ok = false;
+    return 0;
+  }
+  const char* colon = strchr(k, ':');
+  if (!colon || colon > end) {
+    *ok = false;
+    return 0;
+  }
+  return atoll(colon + 1);
+}
+
+// Reads the entries {"counter": ..., "n_lo": ..., "mode": ..., "per_cu": ..., "pair_max":
+// ..., "ms": ...} of a cache written by cs_autotune; unknown or malformed entries are
+// skipped, a missing file gives an empty table.
+TuneTable read_tune(const char* path) {
+  TuneTable t;
+  if (!path || !*path) return t;
+  FILE* f = fopen(path, "r");
+  if (!f) return t;
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+  fclose(f);
+  const char* p = text.c_str();
+  while ((p = strstr(p, "{\"counter\": \"")) != nullptr) {
+    const char* name = p + strlen("{\"counter\": \"");
+    const char* end = strchr(name, '}');
+    if (!end) break;
+    int c = -1;
+    for (int q = 0; q < 3; ++q) {
+      const size_t L = strlen(kCounterName[q]);
+      if (strncmp(name, kCounterName[q], L) == 0 && name[L] == '"') c = q;
+    }
+    bool ok = c >= 0;
+    const long long lo = field_ll(name, end, "\"n_lo\"", &ok);
+    const long long mode = field_ll(name, end, "\"mode\"", &ok);
+    const long long per_cu = field_ll(name, end, "\"per_cu\"", &ok);
+    const long long pmax = field_ll(name, end, "\"pair_max\"", &ok);
+    const char* msk = strstr(name, "\"ms\"");
+    const double ms = (msk && msk < end) ? atof(strchr(msk, ':') + 1) : 0.0;
+    int b = -1;
+    for (int q = 0; q < kBuckets; ++q)
+      if (kBucketLo[q] == lo) b = q;
+    const bool mode_ok = c == 0 ? mode == 0 : (mode == 2 || mode == 4);
+    if (ok && b >= 0 && mode_ok && (per_cu == 1 || per_cu == 2) && !(mode == 4 && per_cu != 1)) {
+      bool has_reps = true;
+      const long long reps = field_ll(name, end, "\"probe_instances\"", &has_reps);
+      t.have[c][b] = true;
+      t.cfg[c][b] = {(int)mode, (int)per_cu, (int)pmax};
+      t.ms[c][b] = ms;
+      t.reps[c][b] = has_reps ? reps : 0;
+    }
+    p = end;
+  }
+  return t;
+}
+
+bool write_tune(const char* path, const TuneTable& t) {
+  FILE* f = fopen(path, "w");
+  if (!f) return false;
+  fprintf(f, "{\n  \"format\": \"causal-batch-tune-2\",\n  \"entries\": [");
+  bool first = true;
+  for (int c = 0; c < 3; ++c)
+    for (int b = 0; b < kBuckets; ++b) {
+      if (!t.have[c][b]) continue;
+      const BatchTile& x = t.cfg[c][b];
+      fprintf(f, "%s\n    {\"counter\": \"%s\", \"n_lo\": %lld, \"n_hi\": %lld, \"mode\": %d, "
+                 "\"tile\": %d, \"per_cu\": %d, \"pair_max\": %d, \"ms\": %.5f, "
+                 "\"probe_n\": %lld, \"probe_instances\": %lld}",
+              first ? "" : ",", kCounterName[c], (long long)kBucketLo[b],
+              (long long)kBucketHi[b], x.mode, x.mode == 4 ? 256 : 128, x.per_cu, x.pair_max,
+              t.ms[c][b], (long long)kBucketProbe[b], (long long)t.reps[c][b]);
+      first = false;
+    }
+  fprintf(f, "\n  ]\n}\n");
+  return fclose(f) == 0;
+}
+
+}  // namespace
+
 struct cs_batch_plan_t {
   int64_t count = 0;
   int counter = CS_COUNT_MFMA;
@@ -32,36 +166,19 @@ struct cs_batch_plan_t {
   std::vector<BatchInst> inst;
   int64_t coords_len = 0, bits_len = 0, hist_len = 0;
   int64_t n_build = 0;
-  int64_t n_items[3] = {0, 0, 0};  // per mode slot: bitset(0), MFMA 128 (1), MFMA 256 (2)
+  int nslots = 0;
+  BatchTile slot_cfg[kMaxSlots] = {};
+  int64_t n_items[kMaxSlots] = {};
   size_t ws_bytes = 0, off_coords = 0, off_bits = 0;
   void* dev = nullptr;              // device tables
   BatchInst* d_inst = nullptr;
   double* d_eps = nullptr;
   uint32_t* d_build = nullptr;
-  uint32_t* d_items[3] = {nullptr, nullptr, nullptr};
+  uint32_t* d_items[kMaxSlots] = {};
   int device = 0;
 };
 
 namespace {
-
-constexpr int kModeOf[3] = {0, 2, 4};
-constexpr int64_t kDefaultTile256MinN = 4096;
-
-int64_t read_tile256_min_n(const char* path) {
-  if (!path || !*path) return kDefaultTile256MinN;
-  FILE* f = fopen(path, "r");
-  if (!f) return kDefaultTile256MinN;
-  char buf[4096];
-  size_t got = fread(buf, 1, sizeof(buf) - 1, f);
-  fclose(f);
-  buf[got] = 0;
-  const char* key = strstr(buf, "\"tile256_min_n\"");
-  if (!key) return kDefaultTile256MinN;
-  const char* colon = strchr(key, ':');
-  if (!colon) return kDefaultTile256MinN;
-  long long v = atoll(colon + 1);
-  return v > 0 ? (int64_t)v : kDefaultTile256MinN;
-}
 
 size_t take(size_t* off, size_t bytes) {
   size_t o = *off;
@@ -69,8 +186,10 @@ size_t take(size_t* off, size_t bytes) {
   return o;
 }
 
+// tune: the cache's choices (entries it lacks use default_tile); force: if not null,
+// every instance takes this configuration (the tuner's candidates).
 cs_status build_plan(int64_t count, const int64_t* n, int counter, int n_eps, const double* eps,
-                     int64_t tile256_min_n, cs_batch_plan_t* p) {
+                     const TuneTable& tune, const BatchTile* force, cs_batch_plan_t* p) {
   p->count = count;
   p->counter = counter;
   p->n_eps = n_eps;
@@ -80,7 +199,8 @@ cs_status build_plan(int64_t count, const int64_t* n, int counter, int n_eps, co
     uint32_t packed;
     int64_t cost;
   };
-  std::vector<Item> items[3];
+  std::vector<Item> items[kMaxSlots];
+  const int cslot = counter_slot(counter);
   int64_t coff = 0, boff = 0, hoff = 0;
   for (int64_t k = 0; k < count; ++k) {
     BatchInst& d = p->inst[k];
@@ -96,8 +216,18 @@ cs_status build_plan(int64_t count, const int64_t* n, int counter, int n_eps, co
     for (int64_t bi = 0; bi < nb; ++bi)
       for (int64_t bj = bi; bj < nb; ++bj)
         build.push_back((uint32_t)(k << 16 | bi << 8 | bj));
-    int slot = counter == CS_COUNT_BITSET ? 0 : (d.n >= tile256_min_n ? 2 : 1);
-    const int64_t BM = slot == 2 ? 256 : 128;
+    const int b = bucket_of(d.n);
+    const BatchTile cfg = force ? *force
+                          : (tune.have[cslot][b] ? tune.cfg[cslot][b] : default_tile(counter, d.n));
+    int slot = -1;
+    for (int q = 0; q < p->nslots; ++q)
+      if (same_tile(p->slot_cfg[q], cfg)) slot = q;
+    if (slot < 0) {
+      if (p->nslots == kMaxSlots) return CS_ERR_UNSUPPORTED;
+      slot = p->nslots++;
+      p->slot_cfg[slot] = cfg;
+    }
+    const int64_t BM = cfg.mode == 4 ? 256 : 128;
     const int64_t T = ceil_div(d.n, BM);
     for (int64_t I = 0; I < T; ++I)  // row panel I: tiles (I, J) for J = I .. T-1
       items[slot].push_back({(uint32_t)(k << 16 | I << 8), (T - I) * (T - I + 1) / 2 * BM * BM * BM});
@@ -106,13 +236,13 @@ cs_status build_plan(int64_t count, const int64_t* n, int counter, int n_eps, co
   p->bits_len = boff;
   p->hist_len = hoff;
   p->n_build = (int64_t)build.size();
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < p->nslots; ++s) {
     std::stable_sort(items[s].begin(), items[s].end(),
                      [](const Item& a, const Item& b) { return a.cost > b.cost; });
     p->n_items[s] = (int64_t)items[s].size();
   }
 
-  // Caller workspace: [3 tile counters][coordinates][matrices].
+  // Caller workspace: [tile counters, one per slot][coordinates][matrices].
   size_t off = 0;
   take(&off, 256);
   p->off_coords = take(&off, sizeof(double) * (size_t)coff);
@@ -124,8 +254,8 @@ cs_status build_plan(int64_t count, const int64_t* n, int counter, int n_eps, co
   size_t o_inst = take(&doff, sizeof(BatchInst) * count);
   size_t o_eps = take(&doff, sizeof(double) * (n_eps > 0 ? n_eps : 1));
   size_t o_build = take(&doff, sizeof(uint32_t) * build.size());
-  size_t o_items[3];
-  for (int s = 0; s < 3; ++s) o_items[s] = take(&doff, sizeof(uint32_t) * items[s].size());
+  size_t o_items[kMaxSlots];
+  for (int s = 0; s < p->nslots; ++s) o_items[s] = take(&doff, sizeof(uint32_t) * items[s].size());
   CS_HIP_CHECK(hipGetDevice(&p->device));
   CS_HIP_CHECK(hipMalloc(&p->dev, doff));
   char* b = (char*)p->dev;
@@ -136,7 +266,7 @@ cs_status build_plan(int64_t count, const int64_t* n, int counter, int n_eps, co
   memcpy(host.data() + o_inst, p->inst.data(), sizeof(BatchInst) * count);
   if (n_eps > 0) memcpy(host.data() + o_eps, eps, sizeof(double) * n_eps);
   memcpy(host.data() + o_build, build.data(), sizeof(uint32_t) * build.size());
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < p->nslots; ++s) {
     p->d_items[s] = (uint32_t*)(b + o_items[s]);
     uint32_t* dst = (uint32_t*)(host.data() + o_items[s]);
     for (size_t q = 0; q < items[s].size(); ++q) dst[q] = items[s][q].packed;
@@ -147,10 +277,10 @@ cs_status build_plan(int64_t count, const int64_t* n, int counter, int n_eps, co
 
 cs_status run_counts(cs_batch_plan_t* p, const uint64_t* bits, uint64_t* hist, unsigned int* ctr,
                      hipStream_t st) {
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < p->nslots; ++s) {
     if (!p->n_items[s]) continue;
-    cs_status r = launch_count_batch(kModeOf[s], p->counter == CS_COUNT_MFMA_FP4, bits, p->d_inst,
-                                     p->d_items[s], p->n_items[s], hist, ctr + s, st);
+    cs_status r = launch_count_batch(p->slot_cfg[s], p->counter == CS_COUNT_MFMA_FP4, bits,
+                                     p->d_inst, p->d_items[s], p->n_items[s], hist, ctr + s, st);
     if (r != CS_OK) return r;
   }
   return CS_OK;
@@ -174,7 +304,7 @@ cs_status cs_batch_plan(int64_t count, const int64_t* n, int counter, int n_eps,
     if (!(eps[e] >= 0.0 && eps[e] <= 1.0)) return CS_ERR_INVALID_ARG;
   cs_batch_plan_t* p = new (std::nothrow) cs_batch_plan_t();
   if (!p) return CS_ERR_HIP;
-  cs_status s = build_plan(count, n, counter, n_eps, eps, read_tile256_min_n(tune_cache), p);
+  cs_status s = build_plan(count, n, counter, n_eps, eps, read_tune(tune_cache), nullptr, p);
   if (s != CS_OK) {
     if (p->dev) (void)hipFree(p->dev);
     delete p;
@@ -204,7 +334,7 @@ cs_status cs_batch_run(cs_batch_plan_handle plan, const uint64_t* seeds, uint64_
   double* coords = (double*)(ws + plan->off_coords);
   uint64_t* bits = (uint64_t*)(ws + plan->off_bits);
   cs_status s;
-  if ((s = launch_fill_u64((uint64_t*)ctr, 2, 0, st)) != CS_OK) return s;
+  if ((s = launch_fill_u64((uint64_t*)ctr, kMaxSlots / 2, 0, st)) != CS_OK) return s;
   if ((s = launch_fill_u64(hist, plan->hist_len, 0, st)) != CS_OK) return s;
   if ((s = launch_sprinkle_batch(seeds, plan->d_inst, plan->count, coords, st)) != CS_OK) return s;
   if ((s = launch_build_batch(coords, plan->d_inst, plan->d_build, plan->n_build, bits, st)) != CS_OK)
@@ -262,84 +392,96 @@ cs_status cs_batch_graph_destroy(void* graph_exec) {
   return CS_OK;
 }
 
-// Measures, for ensembles of `reps` 1+1 diamonds of each size in a fixed ladder, the
-// MFMA counter with 128 and with 256 tiles (best of three launches each, HIP events)
-// and writes the smallest size from which 256 tiles win at every larger size.
-cs_status cs_autotune(const char* cache_path, void* stream) {
+// For each requested (counter, bucket): an ensemble of `reps` diamonds of the bucket's
+// probe size, every tile configuration of the counter's candidates forced on all of them,
+// the counting launches timed (best of three, HIP events); the fastest is stored.
+cs_status cs_autotune(const char* cache_path, int64_t n_bucket, int counter, void* stream) {
   if (!cache_path) return CS_ERR_INVALID_ARG;
+  if (counter != -1 && counter != CS_COUNT_BITSET && counter != CS_COUNT_MFMA &&
+      counter != CS_COUNT_MFMA_FP4)
+    return CS_ERR_UNSUPPORTED;
+  if (n_bucket != 0 && (n_bucket < 2 || n_bucket > kBatchMaxN)) return CS_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
-  const int64_t ladder[] = {512, 1024, 1536, 2048, 3072, 4096, 6144, 8192};
-  const int nl = (int)(sizeof(ladder) / sizeof(ladder[0]));
-  const int64_t reps = 16;
-  double t128[8], t256[8];
+  TuneTable table = read_tune(cache_path);
+  const int cus = device_cu_count();
   hipEvent_t e0, e1;
   CS_HIP_CHECK(hipEventCreate(&e0));
   CS_HIP_CHECK(hipEventCreate(&e1));
   cs_status status = CS_OK;
-  for (int l = 0; l < nl && status == CS_OK; ++l) {
-    std::vector<int64_t> sizes(reps, ladder[l]);
-    double best[2] = {1e30, 1e30};
-    for (int variant = 0; variant < 2 && status == CS_OK; ++variant) {
-      // variant 0: every instance on 128 tiles; variant 1: every instance on 256 tiles
-      cs_batch_plan_t q;
-      status = build_plan(reps, sizes.data(), CS_COUNT_MFMA, 0, nullptr,
-                          variant == 0 ? (int64_t)1 << 40 : 0, &q);
-      if (status != CS_OK) {
+  const int counters[3] = {CS_COUNT_BITSET, CS_COUNT_MFMA, CS_COUNT_MFMA_FP4};
+  for (int ci = 0; ci < 3 && status == CS_OK; ++ci) {
+    const int c = counters[ci];
+    if (counter != -1 && counter != c) continue;
+    const BatchTile* cand = c == CS_COUNT_BITSET ? kBitsetCandidates : kMfmaCandidates;
+    const int ncand = c == CS_COUNT_BITSET
+                          ? (int)(sizeof(kBitsetCandidates) / sizeof(kBitsetCandidates[0]))
+                          : (int)(sizeof(kMfmaCandidates) / sizeof(kMfmaCandidates[0]));
+    for (int b = 0; b < kBuckets && status == CS_OK; ++b) {
+      if (n_bucket != 0 && bucket_of(n_bucket) != b) continue;
+      // Enough instances that the row-panel items of 128-row tiles fill every CU eight
+      // times over, as in a full ensemble (a handful of instances would leave most CUs
+      // idle and favour the wrong occupancy).
+      const int64_t reps = std::max<int64_t>(16, ceil_div(8 * (int64_t)cus,
+                                                          ceil_div(kBucketProbe[b], 128)));
+      std::vector<int64_t> sizes(reps, kBucketProbe[b]);
+      double best_ms = 1e30;
+      int best = -1;
+      for (int v = 0; v < ncand && status == CS_OK; ++v) {
+        cs_batch_plan_t q;
+        status = build_plan(reps, sizes.data(), c, 0, nullptr, TuneTable{}, &cand[v], &q);
+        void* ws = nullptr;
+        uint64_t* hist = nullptr;
+        uint64_t* seeds = nullptr;
+        double ms_v = 1e30;
+        if (status == CS_OK &&
+            (hipMalloc(&ws, q.ws_bytes) != hipSuccess ||
+             hipMalloc((void**)&hist, sizeof(uint64_t) * q.hist_len) != hipSuccess ||
+             hipMalloc((void**)&seeds, sizeof(uint64_t) * reps) != hipSuccess))
+          status = CS_ERR_HIP;
+        if (status == CS_OK) {
+          std::vector<uint64_t> hs(reps);
+          for (int64_t k = 0; k < reps; ++k) hs[k] = 0x5EEDull + 7919ull * k + 104729ull * b;
+          if (hipMemcpy(seeds, hs.data(), sizeof(uint64_t) * reps, hipMemcpyHostToDevice) !=
+              hipSuccess)
+            status = CS_ERR_HIP;
+          if (status == CS_OK) status = cs_batch_run(&q, seeds, hist, nullptr, ws, q.ws_bytes, st);
+          for (int it = 0; it < 3 && status == CS_OK; ++it) {
+            unsigned int* ctr = (unsigned int*)ws;
+            status = launch_fill_u64((uint64_t*)ctr, kMaxSlots / 2, 0, st);
+            if (status == CS_OK) status = launch_fill_u64(hist, q.hist_len, 0, st);
+            if (status != CS_OK) break;
+            (void)hipEventRecord(e0, st);
+            status = run_counts(&q, (uint64_t*)((char*)ws + q.off_bits), hist, ctr, st);
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) status = CS_ERR_HIP;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms_v = std::min(ms_v, (double)ms);
+          }
+        }
+        if (ws) (void)hipFree(ws);
+        if (hist) (void)hipFree(hist);
+        if (seeds) (void)hipFree(seeds);
         if (q.dev) (void)hipFree(q.dev);
-        break;
-      }
-      void* ws = nullptr;
-      uint64_t* hist = nullptr;
-      uint64_t* seeds = nullptr;
-      if (hipMalloc(&ws, q.ws_bytes) != hipSuccess ||
-          hipMalloc((void**)&hist, sizeof(uint64_t) * q.hist_len) != hipSuccess ||
-          hipMalloc((void**)&seeds, sizeof(uint64_t) * reps) != hipSuccess) {
-        status = CS_ERR_HIP;
-      } else {
-        std::vector<uint64_t> hs(reps);
-        for (int64_t k = 0; k < reps; ++k) hs[k] = 0x5EEDull + 7919ull * k + 104729ull * l;
-        (void)hipMemcpy(seeds, hs.data(), sizeof(uint64_t) * reps, hipMemcpyHostToDevice);
-        status = cs_batch_run(&q, seeds, hist, nullptr, ws, q.ws_bytes, st);
-        for (int it = 0; it < 3 && status == CS_OK; ++it) {
-          unsigned int* ctr = (unsigned int*)ws;
-          (void)launch_fill_u64((uint64_t*)ctr, 2, 0, st);
-          (void)launch_fill_u64(hist, q.hist_len, 0, st);
-          (void)hipEventRecord(e0, st);
-          status = run_counts(&q, (uint64_t*)((char*)ws + q.off_bits), hist, ctr, st);
-          (void)hipEventRecord(e1, st);
-          if (hipEventSynchronize(e1) != hipSuccess) status = CS_ERR_HIP;
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          best[variant] = std::min(best[variant], (double)ms);
+        q.dev = nullptr;
+        if (status == CS_OK && ms_v < best_ms) {
+          best_ms = ms_v;
+          best = v;
         }
       }
-      if (ws) (void)hipFree(ws);
-      if (hist) (void)hipFree(hist);
-      if (seeds) (void)hipFree(seeds);
-      if (q.dev) (void)hipFree(q.dev);
-      q.dev = nullptr;
+      if (status == CS_OK && best >= 0) {
+        const int cs_ = counter_slot(c);
+        table.have[cs_][b] = true;
+        table.cfg[cs_][b] = cand[best];
+        table.ms[cs_][b] = best_ms;
+        table.reps[cs_][b] = reps;
+      }
     }
-    t128[l] = best[0];
-    t256[l] = best[1];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (status != CS_OK) return status;
-  int64_t thr = (int64_t)1 << 40;
-  for (int l = nl - 1; l >= 0; --l) {
-    if (t256[l] < t128[l]) thr = ladder[l];
-    else break;
-  }
-  FILE* f = fopen(cache_path, "w");
-  if (!f) return CS_ERR_INVALID_ARG;
-  fprintf(f, "{\n  \"tile256_min_n\": %lld,\n  \"instances_per_size\": %lld,\n  \"ms\": [",
-          (long long)(thr > kBatchMaxN ? kBatchMaxN + 1 : thr), (long long)reps);
-  for (int l = 0; l < nl; ++l)
-    fprintf(f, "%s\n    {\"n\": %lld, \"tile128\": %.4f, \"tile256\": %.4f}", l ? "," : "",
-            (long long)ladder[l], t128[l], t256[l]);
-  fprintf(f, "\n  ]\n}\n");
-  fclose(f);
-  return CS_OK;
+  return write_tune(cache_path, table) ? CS_OK : CS_ERR_INVALID_ARG;
 }
 
 }  // extern "C"

@@ -132,11 +132,19 @@ cs_status launch_sprinkle_batch(const uint64_t* seeds, const BatchInst* inst, in
 cs_status launch_build_batch(const double* coords, const BatchInst* inst,
                              const uint32_t* items, int64_t nitems, uint64_t* bits,
                              hipStream_t st);
-// mode 0: bitset counter (128 tiles); 2 / 4: MFMA counter with 128 / 256 tiles, on the
-// int8 or (fp4 = true) the fp4 matrix cores.
-cs_status launch_count_batch(int mode, bool fp4, const uint64_t* bits, const BatchInst* inst,
-                             const uint32_t* items, int64_t nitems, uint64_t* hist,
-                             unsigned int* counter, hipStream_t st);
+// Launch configuration of an ensemble counter: mode 0 is the bitset counter (128 tiles;
+// tiles with more than pair_max related-pair tasks take the dense product, pair_max < 0:
+// every tile), modes 2 / 4 the MFMA counter with 128 / 256 tiles on the int8 or (fp4 =
+// true) the fp4 matrix cores; per_cu persistent workgroups per compute unit (1 or 2; the
+// 256 tiles fit one).
+struct BatchTile {
+  int mode;
+  int per_cu;
+  int pair_max;
+};
+cs_status launch_count_batch(const BatchTile& cfg, bool fp4, const uint64_t* bits,
+                             const BatchInst* inst, const uint32_t* items, int64_t nitems,
+                             uint64_t* hist, unsigned int* counter, hipStream_t st);
 cs_status launch_action_batch(const uint64_t* hist, const BatchInst* inst, int64_t count,
                               int dim, const double* eps, int n_eps, double* out,
                               hipStream_t st);

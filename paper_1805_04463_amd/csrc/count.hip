@@ -964,6 +964,7 @@ __device__ inline int pair_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs, 
 // are done whatever the mapping of workgroups to XCDs.
 // ===========================================================================
 constexpr int kRA = 4, kRB = 8, kRect = kRA * kRB, kQueues = 8;
+constexpr int64_t kRectMinTiles = 2 * kRect * kQueues;  // below: a single queue
 constexpr int kMaxK = 2048;  // diagonals of the rectangle grid served by the queues (T <= 8184)
 
 struct RectSched {
@@ -1082,9 +1083,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
   uint32_t tmax = 0;
   int64_t pairs_in_lds = 0;
   TileArgs ta{(const uint32_t*)S, 2 * ld, n, 0, 0, hist, f};
-  // Rectangle queues per XCD while the table fits; beyond that (very large n) one queue,
-  // longest K-range first.
-  const bool rect = rect_sched_fits(T);
+  // Rectangle queues per XCD while the table fits and there are enough tiles to share
+  // panels (a workgroup that runs out of work probes every queue once, one global atomic
+  // each, before it exits); otherwise one queue, longest K-range first.
+  const bool rect = rect_sched_fits(T) && T * (T + 1) / 2 >= kRectMinTiles;
   const RectSched rs = rect_sched_make(rect ? T : 1);
   const int x0 = xcc_id();
   const int64_t ntiles = T * (T + 1) / 2;
@@ -1171,10 +1173,12 @@ template <int MODE, bool FP4 = false>
 __global__ __launch_bounds__(kThreads, MODE == 4 ? 1 : 2) void k_count_batch(
     const uint64_t* __restrict__ bits, const BatchInst* __restrict__ inst,
     const uint32_t* __restrict__ items, int64_t nitems, unsigned long long* __restrict__ hist,
-    unsigned int* __restrict__ counter) {
+    unsigned int* __restrict__ counter, int pair_max) {
   constexpr int BM = MODE == 0 ? kBitsetTile : 2 * MODE * 32, HB = kBinsBatch;
   __shared__ typename BatchLdsOf<MODE>::type L;
   for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
+  if constexpr (MODE == 0)
+    if (threadIdx.x < kStageWords) L.Bs[kZeroRow * kStageWords + threadIdx.x] = 0;
   uint32_t tmax = 0;
   int cur = -1;
   TileArgs ta{nullptr, 0, 0, 0, 0, nullptr};
@@ -1198,9 +1202,10 @@ __global__ __launch_bounds__(kThreads, MODE == 4 ? 1 : 2) void k_count_batch(
     ta.I0 = I * BM;
     for (int64_t J = T - 1; J >= I; --J) {
       ta.J0 = J * BM;
-      if constexpr (MODE == 0)
-        bitset_tile<HB>(ta, L.As, L.Bs, L.hist, tmax);
-      else
+      if constexpr (MODE == 0) {
+        if (pair_tile<HB>(ta, L.As, L.Bs, L.pairs, L.hist, tmax, pair_max) == 2)
+          bitset_tile<HB>(ta, L.As, L.Bs, L.hist, tmax);
+      } else
         mfma_tile<MODE, HB, FP4, 0, true>(ta, L.ring, L.rel, L.hist, tmax, nullptr);
     }
   }
@@ -1318,17 +1323,19 @@ cs_status launch_dalembertian(const uint64_t* bits, int64_t n, int64_t ld, int c
   return CS_OK;
 }
 
-cs_status launch_count_batch(int mode, bool fp4, const uint64_t* bits, const BatchInst* inst,
-                             const uint32_t* items, int64_t nitems, uint64_t* hist,
-                             unsigned int* counter, hipStream_t st) {
+cs_status launch_count_batch(const BatchTile& cfg, bool fp4, const uint64_t* bits,
+                             const BatchInst* inst, const uint32_t* items, int64_t nitems,
+                             uint64_t* hist, unsigned int* counter, hipStream_t st) {
   if (nitems <= 0) return CS_OK;
+  const int mode = cfg.mode;
   const int cus = device_cu_count();
-  const int per_cu = mode == 4 ? 1 : 2;
+  const int per_cu = mode == 4 ? 1 : (cfg.per_cu == 1 ? 1 : 2);
+  const int pair_max = cfg.pair_max < 0 ? -1 : std::min(cfg.pair_max, kPairTaskMax);
   const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)cus * per_cu);
   unsigned long long* h = (unsigned long long*)hist;
 #define CS_BATCH_LAUNCH(M, F)                                                                  \
   hipLaunchKernelGGL((k_count_batch<M, F>), dim3(grid), dim3(kThreads), 0, st, bits, inst, \
-                     items, nitems, h, counter)
+                     items, nitems, h, counter, pair_max)
   if (mode == 0) CS_BATCH_LAUNCH(0, false);
   else if (mode == 2 && !fp4) CS_BATCH_LAUNCH(2, false);
   else if (mode == 4 && !fp4) CS_BATCH_LAUNCH(4, false);

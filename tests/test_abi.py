@@ -138,4 +138,7 @@ def test_batch_plan_argument_errors_need_no_device(L):
     assert L.cs_batch_free(None) == 0
     assert L.cs_batch_graph_launch(None, None) == 1
     assert L.cs_batch_graph_destroy(None) == 0
-    assert L.cs_autotune(None, None) == 1
+    assert L.cs_autotune(None, 0, -1, None) == 1
+    assert L.cs_autotune(b"/tmp/x.json", 0, 3, None) == 2         # not an ensemble counter
+    assert L.cs_autotune(b"/tmp/x.json", 9000, 1, None) == 1      # no such bucket
+    assert L.cs_autotune(b"/tmp/x.json", 1, 1, None) == 1

@@ -1,6 +1,7 @@
 """GPU parity of the ensemble path: per-instance N_n bit-exact and actions within 1e-12
-of the oracle's pipeline on each instance; both counters, both MFMA tile shapes, the
-HIP-graph replay, and the 256-instance workload (sampled instances)."""
+of the oracle's pipeline on each instance; every counter with every tile configuration
+the autotuner can choose, the HIP-graph replay, the tuner's cache, and the 256-instance
+workload (sampled instances)."""
 import json
 import os
 
@@ -56,14 +57,32 @@ def test_batch_mixed_sizes(cs, orc, counter):
     check_instances(orc, plan, hist, acts, SIZES, seeds, range(len(SIZES)))
 
 
-@pytest.mark.parametrize("counter", [1, 2], ids=["mfma", "mfma_fp4"])
-@pytest.mark.parametrize("thr", [2, 100000], ids=["all256", "all128"])
-def test_batch_tile_shapes(cs, orc, tmp_path, thr, counter):
-    cache = tmp_path / "tune.json"
-    cache.write_text(json.dumps({"tile256_min_n": thr}))
-    sizes = [130, 700, 2500, 4100, 8000]
-    seeds = [77, 78, 79, 80, 81]
-    plan, hist, acts = run_batch(cs, sizes, seeds, counter, tune_cache=str(cache))
+# Every tile configuration the autotuner can choose: (mode, per_cu, pair_max).
+MFMA_CHOICES = [(2, 2, 0), (2, 1, 0), (4, 1, 0)]
+BITSET_CHOICES = [(0, 2, -1), (0, 2, 1152), (0, 2, 2304), (0, 1, 2304)]
+BUCKETS = [(2, 1023), (1024, 2047), (2048, 4095), (4096, 8192)]
+NAMES = {0: "bitset", 1: "mfma", 2: "mfma_fp4"}
+
+
+def forced_cache(path, counter, choice):
+    """A tuner cache whose entries give `choice` to every size bucket of `counter`."""
+    mode, per_cu, pair_max = choice
+    entries = [{"counter": NAMES[counter], "n_lo": lo, "n_hi": hi, "mode": mode,
+                "tile": 256 if mode == 4 else 128, "per_cu": per_cu, "pair_max": pair_max,
+                "ms": 1.0} for lo, hi in BUCKETS]
+    path.write_text("{\n  \"format\": \"causal-batch-tune-2\",\n  \"entries\": [\n"
+                    + ",\n".join("    " + json.dumps(e) for e in entries) + "\n  ]\n}\n")
+    return str(path)
+
+
+@pytest.mark.parametrize("counter,choice",
+                         [(c, m) for c in (1, 2) for m in MFMA_CHOICES]
+                         + [(0, m) for m in BITSET_CHOICES])
+def test_batch_every_tuner_choice(cs, orc, tmp_path, counter, choice):
+    cache = forced_cache(tmp_path / "tune.json", counter, choice)
+    sizes = [2, 130, 700, 1024, 2500, 4100, 8000, 8192]
+    seeds = [77, 78, 79, 80, 81, 82, 83, 84]
+    plan, hist, acts = run_batch(cs, sizes, seeds, counter, tune_cache=cache)
     check_instances(orc, plan, hist, acts, sizes, seeds, range(len(sizes)))
 
 
@@ -122,10 +141,28 @@ def test_batch_workload_256_counters_agree(cs):
     assert int(h0.sum()) > 0
 
 
-def test_autotune_writes_cache(cs, tmp_path):
+def test_autotune_writes_cache(cs, orc, tmp_path):
+    """Every (counter, bucket) gets an entry naming one of its candidates; tuning one
+    counter and bucket again keeps the other entries; a plan reads the cache."""
     path = tmp_path / "tune.json"
     cs.cs_autotune(str(path))
     torch.cuda.synchronize()
     d = json.loads(path.read_text())
-    assert d["tile256_min_n"] >= 512 and len(d["ms"]) == 8
-    assert all(m["tile128"] > 0 and m["tile256"] > 0 for m in d["ms"])
+    got = {(e["counter"], e["n_lo"]): e for e in d["entries"]}
+    for c, choices in ((0, BITSET_CHOICES), (1, MFMA_CHOICES), (2, MFMA_CHOICES)):
+        for lo, hi in BUCKETS:
+            e = got[(NAMES[c], lo)]
+            assert (e["mode"], e["per_cu"], e["pair_max"]) in choices
+            assert e["n_hi"] == hi and e["ms"] > 0
+    before = path.read_text()
+    cs.cs_autotune(str(path), n_bucket=3000, counter=cs.CS_COUNT_MFMA_FP4)
+    torch.cuda.synchronize()
+    d2 = json.loads(path.read_text())
+    assert len(d2["entries"]) == len(d["entries"])
+    same = [e for e in d2["entries"] if not (e["counter"] == "mfma_fp4" and e["n_lo"] == 2048)]
+    assert all(e in d["entries"] for e in same), before
+    sizes, seeds = [700, 3000, 6000], [1, 2, 3]
+    for c in (0, 1, 2):
+        plan, hist, acts = run_batch(cs, sizes, seeds, c, tune_cache=str(path))
+        check_instances(orc, plan, hist, acts, sizes, seeds, range(len(sizes)))
+

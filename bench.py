@@ -14,6 +14,8 @@ Printed JSON line (rank 0 only):
   mfma, bitset the other counters on the same matrix (R / t, fraction of their peak)
   batch        256 1+1 diamonds of N in [512, 8192]: ensembles/s in one graph launch
                against 256 per-instance launch sequences
+  configs      the 1+1 N=1024 (latency), 3+1 N=16384 and de Sitter N=65536 workloads:
+               whole path and counter kernels, with the oracle timed beside each
   cpu_baseline the CPU oracle's optimised tier timed on a row sample of the same matrix
 """
 from __future__ import annotations
@@ -61,6 +63,9 @@ def parse():
                     help="skip the longest-chain and degree legs")
     ap.add_argument("--no-mink3", action="store_true",
                     help="skip the 2+1 diamond leg (whole path at the same N, fp4 counter)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the smaller configurations (1+1 N=1024, 3+1 N=16384, de Sitter "
+                         "N=65536)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU work for the oracle sample")
@@ -308,6 +313,10 @@ def main():
                         "frac_peak": 2 * useful_macs / (k3 * 1e-3) / PEAKS["mfma_fp4"][0],
                         "actions": {"local": a3[0],
                                     **{f"eps={e}": a for e, a in zip(eps_list, a3[1:])}}}
+
+    if not args.no_configs:
+        from bench_configs import run_configs  # noqa: E402  (lives beside this file)
+        out["configs"] = run_configs(cs, torch, dev, stream, cpu=not args.no_cpu_baseline)
 
     if not args.no_ds2:
         from bench_ds2 import run_ds2  # noqa: E402  (lives beside this file)

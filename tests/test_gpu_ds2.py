@@ -98,21 +98,34 @@ def test_ds2_n131072(cs, orc):
 
 
 def test_ds2_action_approaches_einstein_hilbert(cs):
-    """Sec. 4.3: over ten graphs the mean smeared action approaches S_EH = 4 pi tan(eta0),
-    and its standard deviation grows with N because eps is held fixed."""
+    """Sec. 4.3: the mean smeared action (eps = 2^-6) approaches S_EH = 4 pi tan(eta0) as N
+    grows, and its standard deviation grows with N at fixed eps.  Forty graphs per size (the
+    thesis averages ten; the first ten seeds here are the benchmark's) make the check tight:
+      - at 2^16 and 2^17 the mean is within three standard errors of S_EH (measured: about
+        +-18 % and +-27 % of it);
+      - below that the mean rises towards S_EH with every doubling of N (2^13 -> 2^14 ->
+        2^15), by more than two combined standard errors: a finite-size deficit that shrinks
+        as the smearing scale l / sqrt(eps) shrinks against the slab;
+      - sd(2^17) > sd(2^15) > sd(2^13)."""
     import math
     target = 4 * math.pi * math.tan(ETA0)
+    seeds = range(100, 140)
     stats = {}
-    for n in (1 << 15, 1 << 17):
+    for n in (1 << 13, 1 << 14, 1 << 15, 1 << 16, 1 << 17):
         v = []
-        for seed in W.DS2_SEEDS:
+        for seed in seeds:
             c = cs.cs_sprinkle(W.DS2_SLAB, n, seed, eta0=ETA0)
             b = cs.cs_causal_matrix(W.DS2_SLAB, c)
             h = cs.cs_interval_histogram(b, n, cs.CS_COUNT_MFMA_FP4)
             v.append(cs.cs_action(h, n, 2, EPS).item())
             del b
         v = np.array(v)
-        stats[n] = (v.mean(), v.std(ddof=1))
-    mean, sd = stats[1 << 17]
-    assert abs(mean - target) < 3 * sd / math.sqrt(len(W.DS2_SEEDS)), (mean, sd, target)
-    assert stats[1 << 17][1] > stats[1 << 15][1]
+        stats[n] = (v.mean(), v.std(ddof=1), v.std(ddof=1) / math.sqrt(len(v)))
+    for n in (1 << 16, 1 << 17):
+        mean, _, sem = stats[n]
+        assert abs(mean - target) < 3 * sem, (n, mean, sem, target)
+    for lo, hi in ((1 << 13, 1 << 14), (1 << 14, 1 << 15)):
+        (m0, _, e0), (m1, _, e1) = stats[lo], stats[hi]
+        assert m1 - m0 > 2 * math.hypot(e0, e1), (lo, hi, stats[lo], stats[hi])
+        assert m1 < target
+    assert stats[1 << 17][1] > stats[1 << 15][1] > stats[1 << 13][1]

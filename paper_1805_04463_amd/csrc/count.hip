@@ -252,9 +252,9 @@ template <int BM>
 __device__ inline void dma_one(__amdgpu_buffer_rsrc_t rsrc, uint32_t lds_stage_addr, int32_t voff,
                                int32_t kbyte, int q) {
   const uint32_t wave_off = __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) * 64 * 16);
-  // Rows past n carry an offset of 1 GiB and stages past the last a kbyte of 1 GiB: either
-  // way the request is beyond the descriptor's range (panels are at most 1 GiB) and
-  // reads nothing.  Unsigned, so two such parts add without overflow.
+  // Rows past the panel's valid rows start beyond the descriptor's range, and stages past
+  // the last carry a kbyte of 1 GiB (panels are below 1 GiB): either way the request reads
+  // nothing.  Row part and kbyte are each below 2^30, so their sum does not wrap.
   const uint32_t vo = (uint32_t)voff + (uint32_t)kbyte;
   const uint32_t lds_addr = lds_stage_addr + wave_off + q * kThreads * 16;
   // Issued as inline assembly so the compiler does not add its own wait for the DMA
@@ -269,15 +269,6 @@ __device__ inline void dma_one(__amdgpu_buffer_rsrc_t rsrc, uint32_t lds_stage_a
       : "memory", "m0");
 }
 
-// A whole stage of a BM-row panel (BM*4/256 requests per thread).
-template <int BM>
-__device__ inline void dma_stage(__amdgpu_buffer_rsrc_t rsrc, uint32_t lds_stage_addr,
-                                 const int32_t* voff_row, int32_t kbyte) {
-  constexpr int kPer = BM * 4 / kThreads;
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) dma_one<BM>(rsrc, lds_stage_addr, voff_row[q], kbyte, q);
-}
-
 // Buffer descriptor of a panel (base, byte range), its fields made wave-uniform so they
 // live in scalar registers whatever the compiler can prove about their origin.
 __device__ inline __amdgpu_buffer_rsrc_t uniform_rsrc(const uint32_t* base, uint32_t bytes) {
@@ -289,18 +280,14 @@ __device__ inline __amdgpu_buffer_rsrc_t uniform_rsrc(const uint32_t* base, uint
                                            (int)nr, 0x00020000);
 }
 
-// Panel byte offsets (row part + chunk) of this thread's DMA slots; rows >= n get 1 GiB,
-// past the end of any panel.
-template <int BM>
-__device__ inline void dma_offsets(int32_t* voff_row, int64_t ld, int64_t valid_rows) {
-  constexpr int kPer = BM * 4 / kThreads;
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int slot = q * kThreads + threadIdx.x;
-    const int r = slot >> 2;
-    const int c = (slot & 3) ^ ((r >> 2) & 3);
-    voff_row[q] = r < valid_rows ? (int32_t)(r * ld * 8 + c * 16) : (int32_t)0x40000000;
-  }
+// Panel byte offset of this thread's slot in DMA request 0 of a stage: slot s = tid holds
+// row s/4, 16-byte chunk (s & 3) ^ (row/4 & 3); request q adds 64 rows, which leaves the
+// chunk unchanged, so one register serves every request of both panels (same row stride).
+// Rows past the panel's valid rows lie beyond its descriptor's range (valid rows * ld * 8
+// bytes) and read as zero.
+__device__ inline uint32_t dma_base(int64_t ld) {
+  const uint32_t tid = threadIdx.x;
+  return (tid >> 2) * (uint32_t)(ld * 8) + (((tid & 3u) ^ ((tid >> 4) & 3u)) << 4);
 }
 
 __device__ inline v4i unpack_i8(uint32_t x, uint32_t sh) {
@@ -498,9 +485,8 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
       uniform_rsrc(ta.S32 + I0 * ta.ld32, (uint32_t)(va * ld * 8));
   const __amdgpu_buffer_rsrc_t rbf =
       uniform_rsrc(ta.S32 + J0 * ta.ld32, (uint32_t)(vb * ld * 8));
-  int32_t oa[kPer], ob[kPer];
-  dma_offsets<BM>(oa, ld, va);
-  dma_offsets<BM>(ob, ld, vb);
+  const int32_t vbase = (int32_t)dma_base(ld);
+  const int32_t rows64 = (int32_t)(64 * ld * 8);  // request stride: 64 panel rows, < 2^28
   const int32_t kbyte0 = (int32_t)(kbeg >> 3);
 
   // LDS byte address of the ring (the low 32 bits of a generic LDS pointer).
@@ -514,8 +500,9 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
     constexpr int q = decltype(qc)::value;
     const uint32_t slot = ring_addr + (st % R) * 2 * kStage * 4;
     const int32_t kb = st < nst ? kbyte0 + st * (kMStageBits / 8) : (int32_t)0x40000000;
-    if constexpr (q < kPer) dma_one<BM>(ra, slot, oa[q], kb, q);
-    else dma_one<BM>(rbf, slot + kStage * 4, ob[q - kPer], kb, q - kPer);
+    constexpr int qp = q < kPer ? q : q - kPer;  // request within its panel
+    if constexpr (q < kPer) dma_one<BM>(ra, slot, vbase, kb + qp * rows64, q);
+    else dma_one<BM>(rbf, slot + kStage * 4, vbase, kb + qp * rows64, qp);
   };
   // The previous tile's global histogram atomics: retiring them here leaves the compiler
   // no outstanding memory operation to wait for inside the stage loop.

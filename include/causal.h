@@ -86,9 +86,10 @@ enum {
                               dense product of CS_COUNT_BITSET_DENSE instead              */
     CS_COUNT_MFMA = 1,     /* dense C.C on int8 MFMA (v_mfma_i32_32x32x32_i8), int32 acc  */
     CS_COUNT_MFMA_FP4 = 2, /* dense C.C on fp4 MFMA (v_mfma_scale_f32_32x32x64_f8f6f4,
-                              e2m1 operands 0 / 1.0, unit scales), f32 acc: exact because
-                              every product is 0 or 1 and counts stay below 2^24; needs
-                              n < 2^24 (CS_ERR_OVERFLOW otherwise)                        */
+                              e2m1 operands 0 / 1.0, unit scales), f32 acc started at 2^23:
+                              exact because every product is 0 or 1 and 2^23 + count stays
+                              below 2^24; needs n <= 2^23 + 1 for the histogram (n < 2^24
+                              for the d'Alembertian), CS_ERR_OVERFLOW otherwise           */
     CS_COUNT_BITSET_DENSE = 3  /* VALU AND + popcount over every pair of each tile that
                               holds a related pair (8 x 8 pairs per thread), unrelated
                               pairs discarded at binning: the dense reference of the
@@ -147,7 +148,7 @@ size_t cs_histogram_workspace_bytes(int64_t n, int counter);
  *   workspace device, at least cs_histogram_workspace_bytes(n, counter) bytes.
  * The MFMA counters address a 256-row panel of the matrix with 32-bit offsets and
  * need ld_words <= 2^19 (a panel below 1 GiB, n up to 33.5 million); larger strides
- * give CS_ERR_OVERFLOW.  CS_COUNT_MFMA_FP4 also needs n < 2^24.
+ * give CS_ERR_OVERFLOW.  CS_COUNT_MFMA_FP4 also needs n <= 2^23 + 1.
  */
 cs_status cs_interval_histogram(const uint64_t *bits, int64_t n, int64_t ld_words, int counter,
                                 uint64_t *hist, void *workspace, size_t workspace_bytes,

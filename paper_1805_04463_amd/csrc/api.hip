@@ -13,6 +13,10 @@ constexpr int64_t kMaxN = (int64_t)1 << 31;
 // offsets fit the buffer descriptors' 32-bit range with room for out-of-range requests.
 constexpr int64_t kMaxMfmaLd = (int64_t)1 << 19;
 
+// fp4 histogram: its accumulators start at 2^23 and hold 2^23 + count exactly while
+// counts (at most n - 2) stay below 2^23.
+constexpr int64_t kMaxFp4HistN = ((int64_t)1 << 23) + 2;
+
 // Longest chains: one grid row per pair.
 constexpr int64_t kMaxChainPairs = 65535;
 
@@ -87,7 +91,7 @@ cs_status cs_interval_histogram(const uint64_t* bits, int64_t n, int64_t ld_word
   cs_status s = check_n(n);
   if (s != CS_OK) return s;
   if (!bits || !hist || !workspace || ld_words_ < ld_words(n)) return CS_ERR_INVALID_ARG;
-  if (counter == CS_COUNT_MFMA_FP4 && n >= (int64_t)1 << 24) return CS_ERR_OVERFLOW;
+  if (counter == CS_COUNT_MFMA_FP4 && n >= kMaxFp4HistN) return CS_ERR_OVERFLOW;
   if (is_mfma(counter) && ld_words_ > kMaxMfmaLd) return CS_ERR_OVERFLOW;
   if (workspace_bytes < histogram_ws_bytes(n, counter)) return CS_ERR_WORKSPACE;
   return launch_histogram(bits, n, ld_words_, counter, hist, workspace, as_stream(stream));
@@ -99,7 +103,7 @@ cs_status cs_interval_histogram_noalloc(const uint64_t* bits, int64_t n, int64_t
   cs_status s = check_n(n);
   if (s != CS_OK) return s;
   if (!bits || !hist || ld_words_ < ld_words(n)) return CS_ERR_INVALID_ARG;
-  if (counter == CS_COUNT_MFMA_FP4 && n >= (int64_t)1 << 24) return CS_ERR_OVERFLOW;
+  if (counter == CS_COUNT_MFMA_FP4 && n >= kMaxFp4HistN) return CS_ERR_OVERFLOW;
   if (is_mfma(counter) && ld_words_ > kMaxMfmaLd) return CS_ERR_OVERFLOW;
   if (histogram_ws_bytes(n, counter) > kScratchBytes) return CS_ERR_WORKSPACE;
   void* ws = nullptr;

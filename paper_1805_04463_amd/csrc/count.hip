@@ -560,13 +560,26 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
     if constexpr (FP4) bf[0][nb] = unpack_fp4_class<0>(bw[0][nb]);
     else bf[0][nb] = unpack_i8(bw[0][nb].x, 0u);
   }
+  // fp4 histogram tiles start every accumulator at 2^23: the f32 sum 2^23 + count is then
+  // exact (every addend is an integer and counts stay below 2^23) and its bit pattern is
+  // 0x4B000000 + count, so the epilogue takes integer keys from the bits, without a
+  // conversion.  The other tiles start at 0 and convert.
+  constexpr bool kBias = FP4 && EPI == 0;
+  constexpr uint32_t kB = kBias ? 0x4B000000u : 0u;
   Acc acc[WM][WM];
 #pragma unroll
   for (int a = 0; a < WM; ++a)
 #pragma unroll
     for (int b = 0; b < WM; ++b)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[a][b][e] = 0;
+      for (int e = 0; e < 16; ++e) {
+        if constexpr (kBias) acc[a][b][e] = 8388608.0f;
+        else acc[a][b][e] = 0;
+      }
+  auto key_of = [](auto v) -> uint32_t {  // kB + the count of an accumulator element
+    if constexpr (kBias) return __builtin_bit_cast(uint32_t, v);
+    else return (uint32_t)v;
+  };
 
   auto stage = [&](auto modec, int s) {
     constexpr int MODE = decltype(modec)::value;
@@ -599,8 +612,9 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   // a word past the bins (this lane's own one, or for HB <= key < HB + lane another
   // lane's), which is never flushed, so misses touch no bin.  tmax, the flush range,
   // follows the largest related key.  Counts of HB or more are rare: a second pass over
-  // the block, behind a wave-uniform test, adds them to the global histogram.
-  const uint32_t spare = (uint32_t)HB + (uint32_t)lane;
+  // the block, behind a wave-uniform test, adds them to the global histogram.  Keys carry
+  // the offset kB (fp4) until the LDS address is formed.
+  const uint32_t spare = kB + (uint32_t)HB + (uint32_t)lane;
 #pragma unroll
   for (int nb = 0; nb < WM; ++nb) {
 #pragma unroll
@@ -614,18 +628,18 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
         const int sh = (e >> 2) * 8 + (e & 3);
         // bit sh of wn, sign-extended: all ones for an unrelated pair, zero for a related one
         const uint32_t un = (uint32_t)__builtin_amdgcn_sbfe(wn, sh, 1);
-        const uint32_t key = (uint32_t)acc[mb][nb][e] | un;
+        const uint32_t key = key_of(acc[mb][nb][e]) | un;
         const uint32_t slot = key < spare ? key : spare;
-        atomicAdd(lds_hist + slot, 1u);
+        atomicAdd(lds_hist + (slot - kB), 1u);
         if constexpr (!FITS) big = key + 1u > big ? key + 1u : big;
       }
       if constexpr (FITS) continue;
-      if (big) tmax = big - 1u > tmax ? big - 1u : tmax;
-      if (__ballot(big > (uint32_t)HB)) {
+      if (big) tmax = big - 1u - kB > tmax ? big - 1u - kB : tmax;
+      if (__ballot(big > kB + (uint32_t)HB)) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
           const int sh = (e >> 2) * 8 + (e & 3);
-          const uint32_t bin = (uint32_t)acc[mb][nb][e];
+          const uint32_t bin = key_of(acc[mb][nb][e]) - kB;
           if (((w >> sh) & 1u) && bin >= (uint32_t)HB && (int64_t)bin < nbins)
             atomicAdd(ta.hist + bin, 1ull);
         }

@@ -69,7 +69,9 @@ def test_argument_errors_need_no_device(L):
     assert L.cs_sprinkle(2, 2.0, 1, 100, p, p, 1 << 20, null) == 1
     assert L.cs_sprinkle(1, 0.0, 1, 1000, p, p, 16, null) == 3
     assert L.cs_interval_histogram(p, 100, 8, 1, p, p, 0, null) == 3
-    assert L.cs_interval_histogram(p, 1 << 24, 1 << 18, 2, p, p, 256, null) == 4  # fp4: n < 2^24
+    assert L.cs_interval_histogram(p, 1 << 24, 1 << 18, 2, p, p, 256, null) == 4  # fp4
+    assert L.cs_interval_histogram(p, (1 << 23) + 2, 1 << 18, 2, p, p, 256, null) == 4
+    assert L.cs_interval_histogram(p, (1 << 23) + 2, 1 << 18, 1, p, p, 0, null) == 3  # int8 ok
     # d'Alembertian: dimension, counter, scale, pointers, workspace, sizes
     assert L.cs_dalembertian(p, 100, 8, 5, 1.0, 2, p, p, p, 256, null) == 2
     assert L.cs_dalembertian(p, 100, 8, 2, 1.0, 0, p, p, p, 256, null) == 2

@@ -47,6 +47,7 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kThreads = 256;
 constexpr int kStageBits = 256;         // K bits per LDS stage
 constexpr int kStageWords = kStageBits / 32;
+constexpr int kHalfRows = 129;  // half-major B stage of related-pair tiles: 128 rows + a zero row
 constexpr int kBinsSingle = 12288;      // LDS histogram bins, single instance (48 KiB)
 constexpr int kBinsBatch = 8192;        // LDS histogram bins, ensembles (n <= 8192)
 
@@ -138,15 +139,19 @@ struct Stage {
       v[q] = x;
     }
   }
-  // SWZ: the XOR-swizzled layout of lds_pos (dense tiles); else row r at r * kStageWords,
-  // its halves at +0 and +4 words (related-pair tiles, whose reads take the second half
-  // through the instruction's immediate offset).
-  template <bool SWZ = true>
+  // LAYOUT 0: the XOR-swizzled layout of lds_pos (dense tiles).  1: row r at
+  // r * kStageWords, its halves at +0 and +4 words (A side of related-pair tiles, whose
+  // reads take the second half through the instruction's immediate offset).  2: half-major,
+  // half h of row r at (h * kHalfRows + r) * 4 words (B side of related-pair tiles: lanes
+  // reading the same half of rows a few apart then fall in different bank groups).
+  template <int LAYOUT = 0>
   __device__ inline void store(uint32_t* lds) const {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int c = threadIdx.x + q * kThreads;
-      const int pos = SWZ ? lds_pos(c >> 1, c & 1) : (c >> 1) * kStageWords + (c & 1) * 4;
+      const int r = c >> 1, h = c & 1;
+      const int pos = LAYOUT == 0 ? lds_pos(r, h)
+                      : LAYOUT == 1 ? r * kStageWords + h * 4 : (h * kHalfRows + r) * 4;
       *(uint4*)(lds + pos) = v[q];
     }
   }
@@ -863,13 +868,15 @@ __device__ inline int pair_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs, 
     if (ntask == 0) return 0;
     if (ntask > pair_max) return 2;
     for (int k = 0; k < nt; ++k) P.task[off + k] = (uint16_t)((r << 8) | (kPairGroup * k));
+    // the zero row of both halves of the B stage (the dense path shares the buffer)
+    if (tid < 2 * 4) Bs[((tid >> 2) * kHalfRows + kZeroRow) * 4 + (tid & 3)] = 0u;
   }
   __syncthreads();
 
   // Tasks q * kThreads + tid -> byte offsets of the task row in the A stage and of its
   // columns' rows in the B stage (the zero row where a task has fewer columns).
-  constexpr int kRowBytes = kStageWords * 4;
-  constexpr uint32_t kZeroOff = kZeroRow * kRowBytes;
+  constexpr int kRowBytes = kStageWords * 4;      // A stage: row-major
+  constexpr uint32_t kZeroOff = kZeroRow * 16;      // B stage: half-major, 16 bytes per row
   uint32_t aoff[kPairSlots], boff[kPairSlots][kPairGroup], acc[kPairSlots][kPairGroup];
 #pragma unroll
   for (int q = 0; q < kPairSlots; ++q) {
@@ -897,7 +904,7 @@ __device__ inline int pair_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs, 
       for (int g = 0; g < kPairGroup; ++g) {
         while (x == 0u && w < 3) x = P.rowmask[4 * r + (++w)];
         if (x != 0u) {
-          boff[q][g] = (uint32_t)((32 * w + __ffs(x) - 1) * kRowBytes);
+          boff[q][g] = (uint32_t)((32 * w + __ffs(x) - 1) * 16);
           x &= x - 1u;
         }
       }
@@ -917,8 +924,8 @@ __device__ inline int pair_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs, 
   const char* Bb = (const char*)Bs;
   for (int64_t s = 0; s < nst; ++s) {
     __syncthreads();
-    sa.store<false>(As);
-    sb.store<false>(Bs);
+    sa.store<1>(As);
+    sb.store<2>(Bs);
     __syncthreads();
     if (s + 1 < nst) {
       const int64_t kb = kbeg + (s + 1) * kStageBits;
@@ -933,7 +940,7 @@ __device__ inline int pair_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs, 
           const uint4 a = *(const uint4*)(Ab + aoff[q] + 16 * h);
 #pragma unroll
           for (int g = 0; g < kPairGroup; ++g) {
-            const uint4 b = *(const uint4*)(Bb + boff[q][g] + 16 * h);
+            const uint4 b = *(const uint4*)(Bb + boff[q][g] + 16 * kHalfRows * h);
             acc[q][g] += __popc(a.x & b.x);
             acc[q][g] += __popc(a.y & b.y);
             acc[q][g] += __popc(a.z & b.z);
@@ -1059,7 +1066,7 @@ struct MfmaLds {
 template <int HB>
 struct BitsetLds {
   uint32_t As[kBitsetTile * kStageWords] __attribute__((aligned(16)));
-  uint32_t Bs[(kBitsetTile + 1) * kStageWords] __attribute__((aligned(16)));  // + zero row
+  uint32_t Bs[2 * kHalfRows * 4] __attribute__((aligned(16)));  // dense, or half-major + zero row
   PairLds pairs;
   uint32_t hist[HB];
   uint32_t maxbin;
@@ -1130,7 +1137,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_count_bitset(const uint64_t* __
   const int64_t T = ceil_div(n, BM);
   const int64_t ntiles = T * (T + 1) / 2;
   for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
-  if (threadIdx.x < kStageWords) L.Bs[kZeroRow * kStageWords + threadIdx.x] = 0;
   uint32_t tmax = 0;
   int64_t pairs_in_lds = 0;
   TileArgs ta{(const uint32_t*)S, 2 * ld, n, 0, 0, hist};
@@ -1178,8 +1184,6 @@ __global__ __launch_bounds__(kThreads, MODE == 4 ? 1 : 2) void k_count_batch(
   constexpr int BM = MODE == 0 ? kBitsetTile : 2 * MODE * 32, HB = kBinsBatch;
   __shared__ typename BatchLdsOf<MODE>::type L;
   for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
-  if constexpr (MODE == 0)
-    if (threadIdx.x < kStageWords) L.Bs[kZeroRow * kStageWords + threadIdx.x] = 0;
   uint32_t tmax = 0;
   int cur = -1;
   TileArgs ta{nullptr, 0, 0, 0, 0, nullptr};

@@ -915,22 +915,31 @@ __device__ inline int pair_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs, 
   const int64_t kend = (J0 + BM < n ? J0 + BM : n);
   const int64_t nst = ceil_div(kend - kbeg, kStageBits);
   const int64_t row_bits = ta.ld32 * 32;
-  Stage<BM> sa, sb;
-  sa.init(ta.S32, ta.ld32, I0, n, kbeg);
-  sb.init(ta.S32, ta.ld32, J0, n, kbeg);
-  sa.fetch(0, kbeg, row_bits, I0, kbeg < I0 + BM, true);
-  sb.fetch(0, kbeg, row_bits, J0, kbeg + kStageBits > J0, false);
+  // Two stages in flight through registers (the pair path has little arithmetic per stage
+  // to hide a fetch behind): stage s + 2 is fetched into the buffer stage s just left.
+  Stage<BM> sa[2], sb[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    sa[u].init(ta.S32, ta.ld32, I0, n, kbeg);
+    sb[u].init(ta.S32, ta.ld32, J0, n, kbeg);
+    if (u < nst) {
+      const int64_t kb = kbeg + u * kStageBits;
+      sa[u].fetch(u, kb, row_bits, I0, kb < I0 + BM, true);
+      sb[u].fetch(u, kb, row_bits, J0, kb + kStageBits > J0, false);
+    }
+  }
   const char* Ab = (const char*)As;
   const char* Bb = (const char*)Bs;
-  for (int64_t s = 0; s < nst; ++s) {
+  auto stage = [&](auto uc, int64_t s) {
+    constexpr int u = decltype(uc)::value;
     __syncthreads();
-    sa.store<1>(As);
-    sb.store<2>(Bs);
+    sa[u].template store<1>(As);
+    sb[u].template store<2>(Bs);
     __syncthreads();
-    if (s + 1 < nst) {
-      const int64_t kb = kbeg + (s + 1) * kStageBits;
-      sa.fetch(s + 1, kb, row_bits, I0, kb < I0 + BM, true);
-      sb.fetch(s + 1, kb, row_bits, J0, kb + kStageBits > J0, false);
+    if (s + 2 < nst) {
+      const int64_t kb = kbeg + (s + 2) * kStageBits;
+      sa[u].fetch(s + 2, kb, row_bits, I0, kb < I0 + BM, true);
+      sb[u].fetch(s + 2, kb, row_bits, J0, kb + kStageBits > J0, false);
     }
 #pragma unroll
     for (int q = 0; q < kPairSlots; ++q) {
@@ -949,7 +958,13 @@ __device__ inline int pair_tile(const TileArgs& ta, uint32_t* As, uint32_t* Bs, 
         }
       }
     }
+  };
+  int64_t s = 0;
+  for (; s + 1 < nst; s += 2) {
+    stage(std::integral_constant<int, 0>{}, s);
+    stage(std::integral_constant<int, 1>{}, s + 1);
   }
+  if (s < nst) stage(std::integral_constant<int, 0>{}, s);
 #pragma unroll
   for (int q = 0; q < kPairSlots; ++q)
 #pragma unroll

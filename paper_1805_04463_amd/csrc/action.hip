@@ -140,13 +140,18 @@ constexpr int kActThreads = 1024;
 // The action of one histogram by one workgroup of kActThreads threads.
 // c3: for dim 3, the prefactor in double-double (C_3 / 8 for the local action, whose
 // bracket is taken times 8 to stay an integer; C_3 eps^(2/3) for the smeared one).
-__device__ inline void action_block(const uint64_t* __restrict__ hist, int64_t n, int dim, double eps,
-                                    dd c3, double* __restrict__ out, double* s_hi, double* s_lo) {
+__device__ __attribute__((always_inline)) inline void action_block(
+    const uint64_t* __restrict__ hist, int64_t n, int dim, double eps, dd c3,
+    double* __restrict__ out, double* s_hi, double* s_lo) {
   const int64_t nb = n - 1;
   if (eps == 0.0) {
     if (threadIdx.x == 0) {
-      __int128 h[4] = {0, 0, 0, 0};
-      for (int m = 0; m < 4 && m < nb; ++m) h[m] = (__int128)hist[m];
+      // the first four bins (absent ones are 0), as scalars: no indexed local array
+      const __int128 h0 = (__int128)hist[0];
+      const __int128 h1 = nb > 1 ? (__int128)hist[1] : 0;
+      const __int128 h2 = nb > 2 ? (__int128)hist[2] : 0;
+      const __int128 h3 = nb > 3 ? (__int128)hist[3] : 0;
+      const __int128 h[4] = {h0, h1, h2, h3};
       __int128 I;
       if (dim == 2) {
         I = (__int128)n - 2 * h[0] + 4 * h[1] - 2 * h[2];
@@ -179,21 +184,30 @@ __device__ inline void action_block(const uint64_t* __restrict__ hist, int64_t n
   sm.e = {eps, 0.0};
   sm.q = two_sum(1.0, -eps);
   const int K = dim == 4 ? 3 : 2;
-  for (int k = 0; k <= K; ++k) sm.p[k] = dd_mul(dd_powi(sm.e, k), dd_powi(sm.q, K - k));
+#pragma unroll
+  for (int k = 0; k < 4; ++k)  // constant indices after unrolling (p[3] unused below 3+1)
+    sm.p[k] = k <= K ? dd_mul(dd_powi(sm.e, k), dd_powi(sm.q, K - k)) : dd{0.0, 0.0};
 
-  // Passes of kActThreads chunks of kChunk bins; thread t takes chunk t of each pass and
-  // advances (1-e)^(m-K) by one multiplication per bin.  The weights fall as (1-e)^m:
-  // from the first pass where (1-e)^(m-K) < e^-700 (about 2^-1010) on, a term is at most
-  // 2^-1010 * 2^93 (bracket, m < 2^31) * 2^61 (count), and all of them together stay
-  // below 2^-820, so the passes stop there (near m = 6600 for e = 0.1) instead of
-  // walking all n - 1 bins.
-  constexpr int64_t kChunk = 8;
-  const double log_q = log1p(-eps);  // -inf for eps = 1: only the first pass
+  // The weights fall as (1-e)^m: past the bin where (1-e)^(m-K) < e^-700 (about
+  // 2^-1010) a term is at most 2^-1010 * 2^93 (bracket, m < 2^31) * 2^61 (count), and all
+  // of them together stay below 2^-820, so the walk stops there (near m = 6600 for
+  // e = 0.1) instead of covering all n - 1 bins.
+  const double log_q = log1p(-eps);  // -inf for eps = 1: only the bins up to K
+  int64_t walk = nb;                  // bins up to the cut-off (uniform)
+  if (log_q < 0.0) {
+    const double cut = (double)K + 700.0 / -log_q + 1.0;
+    if (cut < (double)walk) walk = (int64_t)cut;
+  }
+  // One pass: thread t takes the bins [t C, t C + C) of the walk, with C chosen so that
+  // about 512 threads (two waves per SIMD) share it.  Each thread pays once for its first
+  // power (1-e)^(m-K), by repeated squaring, then one multiplication per bin, so fewer
+  // threads with longer chunks do less work in total, down to that occupancy.
+  constexpr int64_t kActBusy = 512;
+  const int64_t chunk = walk <= 4 * kActBusy ? 4 : (walk + kActBusy - 1) / kActBusy;
   dd acc = {0.0, 0.0};
-  for (int64_t base = 0; base < nb; base += kActThreads * kChunk) {
-    if (base > K && (double)(base - K) * log_q < -700.0) break;  // uniform
-    int64_t m = base + (int64_t)threadIdx.x * kChunk;
-    const int64_t m1 = (m + kChunk < nb ? m + kChunk : nb);
+  {
+    int64_t m = (int64_t)threadIdx.x * chunk;
+    const int64_t m1 = m + chunk < walk ? m + chunk : walk;
     for (; m < m1 && m < K; ++m) {
       if (hist[m]) acc = dd_add(acc, dd_mul(dd_from_u64(hist[m]), small_weight(sm, m)));
     }
@@ -206,21 +220,28 @@ __device__ inline void action_block(const uint64_t* __restrict__ hist, int64_t n
       }
     }
   }
-  s_hi[threadIdx.x] = acc.hi;
-  s_lo[threadIdx.x] = acc.lo;
+  // Double-double sum over the workgroup: within each wave by lane exchanges, then the
+  // waves' partial sums through LDS and one barrier.
+  for (int off = 32; off > 0; off >>= 1) {
+    const dd o = {__shfl_xor(acc.hi, off), __shfl_xor(acc.lo, off)};
+    acc = dd_add(acc, o);
+  }
+  constexpr int kWaves = kActThreads / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_hi[wave] = acc.hi;
+    s_lo[wave] = acc.lo;
+  }
   __syncthreads();
-  for (int w = kActThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < (unsigned)w) {
-      dd a = {s_hi[threadIdx.x], s_lo[threadIdx.x]};
-      dd b = {s_hi[threadIdx.x + w], s_lo[threadIdx.x + w]};
-      a = dd_add(a, b);
-      s_hi[threadIdx.x] = a.hi;
-      s_lo[threadIdx.x] = a.lo;
+  if (wave == 0) {
+    acc = lane < kWaves ? dd{s_hi[lane], s_lo[lane]} : dd{0.0, 0.0};
+    for (int off = kWaves / 2; off > 0; off >>= 1) {
+      const dd o = {__shfl_xor(acc.hi, off), __shfl_xor(acc.lo, off)};
+      acc = dd_add(acc, o);
     }
-    __syncthreads();
   }
   if (threadIdx.x == 0) {
-    dd sum = {s_hi[0], s_lo[0]};
+    dd sum = acc;
     dd ec = dim == 2 ? dd{2.0 * eps, 0.0} : dd{eps, 0.0};
     dd br = dd_add(dd{(double)n, 0.0}, dd_mul(dd{-ec.hi, -ec.lo}, sum));
     dd pref;
@@ -243,7 +264,7 @@ __device__ inline void action_block(const uint64_t* __restrict__ hist, int64_t n
 __global__ __launch_bounds__(kActThreads) void k_action(const uint64_t* __restrict__ hist, int64_t n,
                                                         int dim, double eps, double c3hi, double c3lo,
                                                         double* __restrict__ out) {
-  __shared__ double s_hi[kActThreads], s_lo[kActThreads];
+  __shared__ double s_hi[kActThreads / 64], s_lo[kActThreads / 64];  // per wave
   action_block(hist, n, dim, eps, dd{c3hi, c3lo}, out, s_hi, s_lo);
 }
 
@@ -252,7 +273,7 @@ __global__ __launch_bounds__(kActThreads) void k_action_batch(const uint64_t* __
                                                               const BatchInst* __restrict__ inst,
                                                               int dim, const double* __restrict__ eps,
                                                               int n_eps, double* __restrict__ out) {
-  __shared__ double s_hi[kActThreads], s_lo[kActThreads];
+  __shared__ double s_hi[kActThreads / 64], s_lo[kActThreads / 64];  // per wave
   const int k = blockIdx.x / n_eps, e = blockIdx.x % n_eps;
   const BatchInst d = inst[k];
   action_block(hist + d.hist_off, d.n, dim, eps[e], dd{0.0, 0.0}, out + blockIdx.x, s_hi, s_lo);

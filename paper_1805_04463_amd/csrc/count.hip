@@ -1097,8 +1097,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
   constexpr int BM = 2 * WM * 32, HB = kBinsSingle;
   __shared__ MfmaLds<BM, HB> L;  // 96 KiB ring + 48 KiB bins + 8 KiB relation bits at WM = 4
   const int64_t T = ceil_div(n, BM);
-  if constexpr (EPI == 0)
-    for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
+  if constexpr (EPI == 0)  // the bins a count can reach
+    for (int b = threadIdx.x; b < HB && b < n - 1; b += kThreads) L.hist[b] = 0;
   if constexpr (EPI == 1)  // c_m table after the rows' phi (read after the first barrier)
     if (threadIdx.x < 5)
       L.phis[BM + threadIdx.x] = threadIdx.x == 0 ? f.c0 : threadIdx.x == 1 ? f.c1
@@ -1151,7 +1151,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_count_bitset(const uint64_t* __
   __shared__ BitsetLds<HB> L;
   const int64_t T = ceil_div(n, BM);
   const int64_t ntiles = T * (T + 1) / 2;
-  for (int b = threadIdx.x; b < HB; b += kThreads) L.hist[b] = 0;
+  // the bins a count can reach
+  for (int b = threadIdx.x; b < HB && b < n - 1; b += kThreads) L.hist[b] = 0;
   uint32_t tmax = 0;
   int64_t pairs_in_lds = 0;
   TileArgs ta{(const uint32_t*)S, 2 * ld, n, 0, 0, hist};
@@ -1237,6 +1238,13 @@ __global__ void k_fill_u64(uint64_t* __restrict__ p, int64_t count, uint64_t val
   if (i < count) p[i] = value;
 }
 
+// Zeroes two ranges in one launch (an output and the work-queue counters).
+__global__ void k_zero2(uint64_t* __restrict__ a, int64_t na, uint64_t* __restrict__ b, int64_t nb) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < na) a[i] = 0;
+  else if (i - na < nb) b[i - na] = 0;
+}
+
 }  // namespace
 
 int device_cu_count() {
@@ -1249,6 +1257,13 @@ int device_cu_count() {
     if (cus <= 0) cus = 256;
   }
   return cus;
+}
+
+cs_status launch_zero2(uint64_t* a, int64_t na, uint64_t* b, int64_t nb, hipStream_t st) {
+  if (na + nb <= 0) return CS_OK;
+  hipLaunchKernelGGL(k_zero2, dim3((unsigned)ceil_div(na + nb, 256)), dim3(256), 0, st, a, na, b, nb);
+  CS_LAUNCH_CHECK();
+  return CS_OK;
 }
 
 cs_status launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream_t st) {
@@ -1283,9 +1298,7 @@ __global__ void k_field_finish(const double* __restrict__ phi, double* __restric
 cs_status launch_histogram(const uint64_t* bits, int64_t n, int64_t ld, int counter, uint64_t* hist,
                            void* ws, hipStream_t st) {
   unsigned int* ctr = (unsigned int*)ws;
-  cs_status s = launch_fill_u64(hist, n - 1, 0, st);
-  if (s != CS_OK) return s;
-  s = launch_fill_u64((uint64_t*)ws, 4, 0, st);  // 8 queue counters
+  cs_status s = launch_zero2(hist, n - 1, (uint64_t*)ws, 4, st);  // bins, 8 queue counters
   if (s != CS_OK) return s;
   const bool big = n > 4096;  // 256x256 output tiles above 4096 points, 128x128 below
   switch (counter) {
@@ -1312,9 +1325,8 @@ size_t field_ws_bytes(int64_t, int) { return 256; }
 cs_status launch_dalembertian(const uint64_t* bits, int64_t n, int64_t ld, int counter, int dim,
                               double ell, const double* phi, double* out, void* ws, hipStream_t st) {
   unsigned int* ctr = (unsigned int*)ws;
-  cs_status s = launch_fill_u64((uint64_t*)out, n, 0, st);  // +0.0
-  if (s != CS_OK) return s;
-  s = launch_fill_u64((uint64_t*)ws, 4, 0, st);  // 8 queue counters
+  // out = +0.0, 8 queue counters
+  cs_status s = launch_zero2((uint64_t*)out, n, (uint64_t*)ws, 4, st);
   if (s != CS_OK) return s;
   // Eqs. b2d_local, b3d_local, b4d_local: K / ell^2 [-phi(j) + sum_m c_m sum_{L_m(j)} phi(i)].
   FieldArgs f{phi, out, 0.0, 0.0, 0.0, 0.0};

@@ -306,6 +306,21 @@ __device__ inline void cmp_swap_lds(uint64_t* sk, uint32_t* sg, int i, int l, bo
   }
 }
 
+// Orders a bitonic compare-exchange step after the previous one.  A step of distance
+// j <= 64 pairs thread t (of a wave's 64) with elements inside the 128-element block
+// t / 64 (in steps of 64 threads), so each block belongs to one wave: such a step needs
+// only the wave's own earlier LDS writes.  Steps of larger distance, and the first step
+// after another step of larger distance or after loading, synchronise the workgroup.
+__device__ inline void bitonic_step_sync(bool workgroup) {
+  if (workgroup) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 // kfirst == 0: full sort of each chunk (k = 2 .. CH).  Otherwise: the j < CH steps of
 // merge stage k = kfirst.  One thread per pair; CH/2 threads per block.
 __global__ void k_bitonic_lds(uint64_t* __restrict__ keys, uint32_t* __restrict__ gens, int CH,
@@ -320,10 +335,12 @@ __global__ void k_bitonic_lds(uint64_t* __restrict__ keys, uint32_t* __restrict_
   sg[t + CH / 2] = gens[base + t + CH / 2];
   int64_t k0 = kfirst ? kfirst : 2;
   int64_t k1 = kfirst ? kfirst : CH;
+  bool wide = true;  // the previous step (or the load) crossed 128-element blocks
   for (int64_t k = k0; k <= k1; k <<= 1) {
     int jstart = (int)((k >> 1) < (CH >> 1) ? (k >> 1) : (CH >> 1));
     for (int j = jstart; j > 0; j >>= 1) {
-      __syncthreads();
+      bitonic_step_sync(wide || j >= 128);
+      wide = j >= 128;
       int i = 2 * t - (t & (j - 1));
       bool asc = ((base + i) & k) == 0;
       cmp_swap_lds(sk, sg, i, i + j, asc);
@@ -357,6 +374,63 @@ __global__ void k_gather(const double* __restrict__ raw, const uint32_t* __restr
   if (i >= n) return;
   uint32_t g = gens[i];
   for (int p = 0; p < planes; ++p) coords[(int64_t)p * n + i] = raw[(int64_t)p * n + g];
+}
+
+// ---------------------------------------------------------------------------
+// Small sets: the time order by ranks.  Element g's place is the number of elements
+// before it in (key, index) order, the order the sort network produces; the place is
+// counted over every key and the coordinates are written straight there, which replaces
+// the sort and the gather by one launch.  Sixteen lanes share an element, each comparing
+// against every sixteenth key of a chunk staged in LDS (consecutive lanes read
+// consecutive words, so a wave's reads hit distinct banks); the partial counts are summed
+// by lane exchanges.  Equal keys are rare: a wave with one runs a second pass that
+// counts the equal keys of smaller index.
+// ---------------------------------------------------------------------------
+constexpr int kRankThreads = 256;
+constexpr int kRankSplit = 16;                       // lanes per element
+constexpr int kRankPer = kRankThreads / kRankSplit;  // elements per workgroup
+constexpr int kRankChunk = 2048;                     // keys staged per pass
+constexpr int64_t kRankMaxN = 8192;                  // n^2 comparisons: small sets only
+
+__device__ inline uint32_t rank_lane_sum(uint32_t v) {
+#pragma unroll
+  for (int off = kRankSplit / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__global__ __launch_bounds__(kRankThreads) void k_rank_place(const uint64_t* __restrict__ keys,
+                                                             const double* __restrict__ raw,
+                                                             int planes, int64_t n,
+                                                             double* __restrict__ coords) {
+  __shared__ uint64_t sk[kRankChunk];
+  const int s = threadIdx.x & (kRankSplit - 1);
+  const int64_t g = (int64_t)blockIdx.x * kRankPer + threadIdx.x / kRankSplit;
+  const bool live = g < n;
+  const uint64_t kg = live ? keys[g] : 0ull;
+  uint32_t lt = 0, eq = 0;
+  for (int64_t base = 0; base < n; base += kRankChunk) {
+    const int m = (int)(n - base < kRankChunk ? n - base : kRankChunk);
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += kRankThreads) sk[i] = keys[base + i];
+    __syncthreads();
+#pragma unroll 8
+    for (int i = s; i < m; i += kRankSplit) {
+      const uint64_t kh = sk[i];
+      lt += kh < kg ? 1u : 0u;
+      eq += kh == kg ? 1u : 0u;
+    }
+  }
+  lt = rank_lane_sum(lt);
+  eq = rank_lane_sum(eq);
+  const bool tie = live && eq > 1u;  // another element carries the same key
+  if (__ballot(tie)) {
+    uint32_t before = 0;
+    if (tie)
+      for (int64_t h = s; h < g; h += kRankSplit) before += keys[h] == kg ? 1u : 0u;
+    lt += rank_lane_sum(before);
+  }
+  if (live)
+    for (int p = s; p < planes; p += kRankSplit) coords[(int64_t)p * n + lt] = raw[(int64_t)p * n + g];
 }
 
 cs_status bitonic_sort(uint64_t* keys, uint32_t* gens, int64_t P, hipStream_t st) {
@@ -403,9 +477,13 @@ __global__ __launch_bounds__(kBatchSortThreads) void k_sprinkle_mink2_batch(
       sg[g] = 0xFFFFFFFFu;
     }
   }
+  bool wide = true;  // the previous step (or the load) crossed 128-element blocks
   for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      __syncthreads();
+      // pairs t, t + 1024, ... of thread t: with j <= 64 every 128-element block is
+      // still worked by one wave (block b by wave b mod 16)
+      bitonic_step_sync(wide || j >= 128);
+      wide = j >= 128;
       for (int t = threadIdx.x; t < P / 2; t += kBatchSortThreads) {
         const int i = 2 * t - (t & (j - 1));
         cmp_swap_lds(sk, sg, i, i + j, (i & k) == 0);
@@ -473,6 +551,12 @@ cs_status launch_sprinkle(int region, double eta0, uint64_t seed, int64_t n, dou
                        sm_stream_key(seed, kStreamDsTime), sm_stream_key(seed, kStreamDsSphere),
                        tan(eta0), n, P, w.raw, w.keys, w.gens);
     CS_LAUNCH_CHECK();
+  }
+  if (n <= kRankMaxN) {
+    hipLaunchKernelGGL(k_rank_place, dim3((unsigned)ceil_div(n, kRankPer)), dim3(kRankThreads), 0,
+                       st, w.keys, w.raw, planes, n, coords);
+    CS_LAUNCH_CHECK();
+    return CS_OK;
   }
   cs_status s = bitonic_sort(w.keys, w.gens, P, st);
   if (s != CS_OK) return s;

@@ -1113,6 +1113,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
   const RectSched rs = rect_sched_make(rect ? T : 1);
   const int x0 = xcc_id();
   const int64_t ntiles = T * (T + 1) / 2;
+  // Small matrices launch a workgroup per tile: each takes the tile of its own index,
+  // without the queue's two atomic round trips.
+  const bool direct = !rect && ntiles <= (int64_t)gridDim.x;
+  bool taken = false;
   int probe = 0;
   for (;;) {
     int64_t I, J;
@@ -1126,8 +1130,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
       }
       if (!rect_tile(rs, x, q, &I, &J)) continue;
     } else {
-      const int64_t t = next_tile(counter, &L.slot);
-      if (t >= ntiles) break;
+      int64_t t;
+      if (direct) {
+        if (taken) break;
+        taken = true;
+        t = blockIdx.x;
+      } else {
+        t = next_tile(counter, &L.slot);
+        if (t >= ntiles) break;
+      }
       tile_of(t, T, &I, &J);
     }
     if (EPI == 0 && pairs_in_lds > (1ll << 31) - (int64_t)BM * BM) {  // uint32 LDS bins exact

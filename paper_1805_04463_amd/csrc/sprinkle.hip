@@ -4,7 +4,9 @@
 //
 // Pipeline per call: generate raw SoA coordinates + a 64-bit time key per point
 // -> bitonic sort of (key, generation index) pairs (LDS chunks of 2048 + global
-// merge steps) -> gather the coordinate planes into sorted order.
+// merge steps) -> gather the coordinate planes into sorted order.  Sets of at most
+// 8192 points skip the sort and the gather: each point's rank is counted over all
+// keys and its planes are written there.
 // The 3+1 diamond is sampled by rejection: candidates are flagged, counted per
 // block, scanned, and the first n accepted are scattered in candidate order.
 #include "common.h"

@@ -385,8 +385,8 @@ __global__ void k_gather(const double* __restrict__ raw, const uint32_t* __restr
 // the sort and the gather by one launch.  Sixteen lanes share an element, each comparing
 // against every sixteenth key of a chunk staged in LDS (consecutive lanes read
 // consecutive words, so a wave's reads hit distinct banks); the partial counts are summed
-// by lane exchanges.  Equal keys are rare: a wave with one runs a second pass that
-// counts the equal keys of smaller index.
+// by lane exchanges.  Each comparison is the order itself, key first and index on equal
+// keys, so equal keys need no separate pass.
 // ---------------------------------------------------------------------------
 constexpr int kRankThreads = 256;
 constexpr int kRankSplit = 16;                       // lanes per element
@@ -409,28 +409,20 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_place(const uint64_t* __r
   const int64_t g = (int64_t)blockIdx.x * kRankPer + threadIdx.x / kRankSplit;
   const bool live = g < n;
   const uint64_t kg = live ? keys[g] : 0ull;
-  uint32_t lt = 0, eq = 0;
+  uint32_t before = 0;  // elements h with (key_h, h) < (key_g, g)
   for (int64_t base = 0; base < n; base += kRankChunk) {
     const int m = (int)(n - base < kRankChunk ? n - base : kRankChunk);
     __syncthreads();
     for (int i = threadIdx.x; i < m; i += kRankThreads) sk[i] = keys[base + i];
     __syncthreads();
+    const int gi = (int)(g - base);  // g's index within the chunk (any value if outside)
 #pragma unroll 8
     for (int i = s; i < m; i += kRankSplit) {
       const uint64_t kh = sk[i];
-      lt += kh < kg ? 1u : 0u;
-      eq += kh == kg ? 1u : 0u;
+      before += (kh < kg || (kh == kg && i < gi)) ? 1u : 0u;
     }
   }
-  lt = rank_lane_sum(lt);
-  eq = rank_lane_sum(eq);
-  const bool tie = live && eq > 1u;  // another element carries the same key
-  if (__ballot(tie)) {
-    uint32_t before = 0;
-    if (tie)
-      for (int64_t h = s; h < g; h += kRankSplit) before += keys[h] == kg ? 1u : 0u;
-    lt += rank_lane_sum(before);
-  }
+  const uint32_t lt = rank_lane_sum(before);
   if (live)
     for (int p = s; p < planes; p += kRankSplit) coords[(int64_t)p * n + lt] = raw[(int64_t)p * n + g];
 }

@@ -142,9 +142,16 @@ struct BatchTile {
   int per_cu;
   int pair_max;
 };
+// An ensemble counter's work list in one queue per XCD: queue x is items[off[x] .. off[x+1]).
+constexpr int kBatchQueues = 8;
+struct BatchQueues {
+  uint32_t off[kBatchQueues + 1];
+};
+// counter: kBatchQueues work counters, zero at launch.
 cs_status launch_count_batch(const BatchTile& cfg, bool fp4, const uint64_t* bits,
-                             const BatchInst* inst, const uint32_t* items, int64_t nitems,
-                             uint64_t* hist, unsigned int* counter, hipStream_t st);
+                             const BatchInst* inst, const uint32_t* items,
+                             const BatchQueues& queues, uint64_t* hist, unsigned int* counter,
+                             hipStream_t st);
 cs_status launch_action_batch(const uint64_t* hist, const BatchInst* inst, int64_t count,
                               int dim, const double* eps, int n_eps, double* out,
                               hipStream_t st);

@@ -1188,7 +1188,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_count_bitset(const uint64_t* __
 // ===========================================================================
 // Ensemble kernels: persistent over packed row-panel items (instance << 16 | I << 8):
 // one item is every tile (I, J >= I) of one instance's row panel I, longest first.
-// Items are ordered by cost across all instances.  The LDS histogram belongs to one
+// The items sit in one queue per XCD, each queue whole instances one after another: a
+// workgroup serves the queue of the XCD it runs on (hardware register XCC_ID), so the
+// workgroups of an XCD work on the same matrix at once and share its panels in that
+// XCD's L2, then takes work from the other queues.  The LDS histogram belongs to one
 // instance at a time and is flushed when the workgroup moves to another instance.
 // Instance sizes are at most 8192, so every bin fits in LDS.
 // ===========================================================================
@@ -1206,7 +1209,7 @@ static_assert(kBinsBatch >= kBatchMaxN - 1, "ensemble counts fit the LDS bins");
 template <int MODE, bool FP4 = false>
 __global__ __launch_bounds__(kThreads, MODE == 4 ? 1 : 2) void k_count_batch(
     const uint64_t* __restrict__ bits, const BatchInst* __restrict__ inst,
-    const uint32_t* __restrict__ items, int64_t nitems, unsigned long long* __restrict__ hist,
+    const uint32_t* __restrict__ items, BatchQueues queues, unsigned long long* __restrict__ hist,
     unsigned int* __restrict__ counter, int pair_max) {
   constexpr int BM = MODE == 0 ? kBitsetTile : 2 * MODE * 32, HB = kBinsBatch;
   __shared__ typename BatchLdsOf<MODE>::type L;
@@ -1214,10 +1217,17 @@ __global__ __launch_bounds__(kThreads, MODE == 4 ? 1 : 2) void k_count_batch(
   uint32_t tmax = 0;
   int cur = -1;
   TileArgs ta{nullptr, 0, 0, 0, 0, nullptr};
+  const int x0 = xcc_id();
+  int probe = 0;
   for (;;) {
-    const int64_t t = next_tile(counter, &L.slot);
-    if (t >= nitems) break;
-    const uint32_t it = items[t];
+    if (probe >= kBatchQueues) break;
+    const int x = (x0 + probe) & (kBatchQueues - 1);
+    const int64_t q = next_tile(counter + x, &L.slot);
+    if (q >= (int64_t)(queues.off[x + 1] - queues.off[x])) {
+      ++probe;
+      continue;
+    }
+    const uint32_t it = items[queues.off[x] + q];
     const int k = (int)(it >> 16);
     if (k != cur) {
       if (cur >= 0) flush_hist<HB>(L.hist, ta.hist, ta.n - 1, tmax, &L.maxbin);
@@ -1367,8 +1377,10 @@ cs_status launch_dalembertian(const uint64_t* bits, int64_t n, int64_t ld, int c
 }
 
 cs_status launch_count_batch(const BatchTile& cfg, bool fp4, const uint64_t* bits,
-                             const BatchInst* inst, const uint32_t* items, int64_t nitems,
-                             uint64_t* hist, unsigned int* counter, hipStream_t st) {
+                             const BatchInst* inst, const uint32_t* items,
+                             const BatchQueues& queues, uint64_t* hist, unsigned int* counter,
+                             hipStream_t st) {
+  const int64_t nitems = queues.off[kBatchQueues];
   if (nitems <= 0) return CS_OK;
   const int mode = cfg.mode;
   const int cus = device_cu_count();
@@ -1378,7 +1390,7 @@ cs_status launch_count_batch(const BatchTile& cfg, bool fp4, const uint64_t* bit
   unsigned long long* h = (unsigned long long*)hist;
 #define CS_BATCH_LAUNCH(M, F)                                                                  \
   hipLaunchKernelGGL((k_count_batch<M, F>), dim3(grid), dim3(kThreads), 0, st, bits, inst, \
-                     items, nitems, h, counter, pair_max)
+                     items, queues, h, counter, pair_max)
   if (mode == 0) CS_BATCH_LAUNCH(0, false);
   else if (mode == 2 && !fp4) CS_BATCH_LAUNCH(2, false);
   else if (mode == 4 && !fp4) CS_BATCH_LAUNCH(4, false);

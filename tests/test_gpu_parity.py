@@ -45,8 +45,10 @@ def ulps(a, b):
 REGIONS = [W.MINK2_DIAMOND, W.MINK4_DIAMOND, W.DS4_SLAB]
 
 
-@pytest.mark.parametrize("region", [W.MINK2_DIAMOND, W.MINK4_DIAMOND])
-@pytest.mark.parametrize("n", [2, 3, 100, 2047, 2048, 2049, 5000])
+# 8192 is the largest set ordered by rank placement, 8193 the smallest ordered by the sort
+# network and gather; 2047-2049 straddle the network's LDS chunk.
+@pytest.mark.parametrize("region", [W.MINK2_DIAMOND, W.MINK4_DIAMOND, W.MINK3_DIAMOND])
+@pytest.mark.parametrize("n", [2, 3, 100, 2047, 2048, 2049, 5000, 8192, 8193])
 def test_sprinkle_minkowski_bit_exact(cs, orc, region, n):
     want = orc.sprinkle(region, n, seed=1000 + n)
     got = cs.cs_sprinkle(region, n, seed=1000 + n).cpu().numpy()

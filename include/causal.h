@@ -300,9 +300,10 @@ cs_status cs_batch_graph_destroy(void *graph_exec);
  * Tile autotuner (project-written) of the ensemble counters.  Instance sizes fall in four
  * buckets, [2, 1023], [1024, 2047], [2048, 4095] and [4096, 8192].  For each requested
  * counter and bucket it times, on the current device, every tile configuration of the
- * counter on an ensemble of diamonds of one size in the bucket (768, 1536, 3072 or 6144
- * points; enough of them that their row panels of 128-row tiles number eight per compute
- * unit, at least 16; the counting launches only, best of three, HIP events on `stream`):
+ * counter on an ensemble of diamonds with sizes spread evenly around the bucket's centre
+ * (768, 1536, 3072 or 6144 points, from 2c - hi to hi; enough of them that their row
+ * panels of 128-row tiles number sixteen per compute unit, at least 16; the counting
+ * launches only, best of five, HIP events on `stream`):
  *   CS_COUNT_MFMA, CS_COUNT_MFMA_FP4: 128x128 output tiles with two or with one
  *       persistent workgroup per compute unit, 256x256 tiles with one;
  *   CS_COUNT_BITSET: related-pair tiles with at most 2304 or 1152 tasks (denser tiles

@@ -38,7 +38,7 @@ namespace {
 
 constexpr int kMaxSlots = 8;  // distinct tile configurations in one plan
 
-// Size buckets of the tuner: [lo, hi] and the size timed for each.
+// Size buckets of the tuner: [lo, hi] and the centre of the sizes timed for each.
 constexpr int kBuckets = 4;
 constexpr int64_t kBucketLo[kBuckets] = {2, 1024, 2048, 4096};
 constexpr int64_t kBucketHi[kBuckets] = {1023, 2047, 4095, kBatchMaxN};
@@ -461,12 +461,17 @@ cs_status cs_autotune(const char* cache_path, int64_t n_bucket, int counter, voi
                           : (int)(sizeof(kMfmaCandidates) / sizeof(kMfmaCandidates[0]));
     for (int b = 0; b < kBuckets && status == CS_OK; ++b) {
       if (n_bucket != 0 && bucket_of(n_bucket) != b) continue;
-      // Enough instances that the row-panel items of 128-row tiles fill every CU eight
+      // Enough instances that the row-panel items of 128-row tiles fill every CU sixteen
       // times over, as in a full ensemble (a handful of instances would leave most CUs
-      // idle and favour the wrong occupancy).
-      const int64_t reps = std::max<int64_t>(16, ceil_div(8 * (int64_t)cus,
+      // idle and favour the wrong occupancy; eight times over left candidates within the
+      // timing noise of each other that differ by 8 % in a full ensemble).
+      const int64_t reps = std::max<int64_t>(16, ceil_div(16 * (int64_t)cus,
                                                           ceil_div(kBucketProbe[b], 128)));
-      std::vector<int64_t> sizes(reps, kBucketProbe[b]);
+      // Sizes spread evenly over the bucket, centred on its probe size, as in an ensemble
+      // of uneven instances (identical ones would all end at once and favour other tiles).
+      const int64_t plo = 2 * kBucketProbe[b] - kBucketHi[b], phi = kBucketHi[b];
+      std::vector<int64_t> sizes(reps);
+      for (int64_t k = 0; k < reps; ++k) sizes[k] = plo + (phi - plo) * k / (reps - 1);
       double best_ms = 1e30;
       int best = -1;
       for (int v = 0; v < ncand && status == CS_OK; ++v) {
@@ -488,7 +493,7 @@ cs_status cs_autotune(const char* cache_path, int64_t n_bucket, int counter, voi
               hipSuccess)
             status = CS_ERR_HIP;
           if (status == CS_OK) status = cs_batch_run(&q, seeds, hist, nullptr, ws, q.ws_bytes, st);
-          for (int it = 0; it < 3 && status == CS_OK; ++it) {
+          for (int it = 0; it < 5 && status == CS_OK; ++it) {
             unsigned int* ctr = (unsigned int*)ws;
             status = launch_fill_u64((uint64_t*)ctr, kMaxSlots * kBatchQueues / 2, 0, st);
             if (status == CS_OK) status = launch_fill_u64(hist, q.hist_len, 0, st);

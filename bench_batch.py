@@ -43,12 +43,22 @@ def run_batch(cs, torch, dev, stream, reps: int = 5):
     out = {"instances": count, "n_range": [int(sizes.min()), int(sizes.max())],
            "autotune": {"seconds": tune_s, "choices": tuned}}
     results = {}
-    # each counter with the tuned tiles; the fp4 counter also with the library's default
-    # tiles (no cache), to show what the tuner changes
+    # The fp4 counter also with 256x256 tiles (one workgroup per CU) for the instances of
+    # 4096 points or more, the tuner's other candidate there, to show what its choice is
+    # worth; a cache file of the tuner's format gives that configuration.
+    alt = os.path.join(tempfile.gettempdir(), "cs_tune_fp4_tiles256.json")
+    ent = [{"counter": "mfma_fp4", "n_lo": lo, "n_hi": hi, "mode": 4 if lo >= 4096 else 2,
+            "tile": 256 if lo >= 4096 else 128, "per_cu": 1 if lo >= 4096 else 2,
+            "pair_max": 0, "ms": 0.0}
+           for lo, hi in ((2, 1023), (1024, 2047), (2048, 4095), (4096, 8192))]
+    with open(alt, "w") as f:
+        f.write('{\n  "format": "causal-batch-tune-2",\n  "entries": [\n'
+                + ",\n".join("    " + json.dumps(e) for e in ent) + "\n  ]\n}\n")
+    # each counter with the tuned tiles
     for name, counter, cache in (("mfma", cs.CS_COUNT_MFMA, tune),
                                  ("mfma_fp4", cs.CS_COUNT_MFMA_FP4, tune),
                                  ("bitset", cs.CS_COUNT_BITSET, tune),
-                                 ("mfma_fp4_default_tiles", cs.CS_COUNT_MFMA_FP4, None)):
+                                 ("mfma_fp4_tiles256_from4096", cs.CS_COUNT_MFMA_FP4, alt)):
         plan = cs.BatchPlan(sizes, counter=counter, eps=eps, tune_cache=cache)
         s = torch.from_numpy(seeds.view(np.int64)).to(dev)
         hist = torch.empty(plan.hist_len, dtype=torch.int64, device=dev)

@@ -314,8 +314,8 @@ cs_status cs_batch_graph_destroy(void *graph_exec);
  * The fastest configuration of each (counter, bucket) is stored in the JSON file
  * cache_path (one entry per line, keeping the entries of an existing file that were not
  * re-tuned).  cs_batch_plan reads its own counter's entries from `tune_cache` (may be
- * NULL); without an entry it uses 128 tiles below 4096 points and 256 tiles from 4096
- * (MFMA), related-pair tiles with at most 2304 tasks (bitset).  The tuner allocates and
+ * NULL); without an entry it uses 128 tiles with two workgroups per CU (MFMA) and
+ * related-pair tiles with at most 2304 tasks (bitset).  The tuner allocates and
  * frees its own device memory and synchronises `stream`.  Every configuration gives
  * identical, exact histograms.
  */

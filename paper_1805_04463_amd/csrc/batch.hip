@@ -65,7 +65,8 @@ const BatchTile kBitsetCandidates[] = {{0, 2, -1}, {0, 2, 1152}, {0, 2, 2304}, {
 // tiles from there; the bitset counter on related-pair tiles with the largest task list.
 BatchTile default_tile(int counter, int64_t n) {
   if (counter == CS_COUNT_BITSET) return {0, 2, 2304};
-  return n >= 4096 ? BatchTile{4, 1, 0} : BatchTile{2, 2, 0};
+  (void)n;  // 128-row tiles, two workgroups per CU: the tuner's choice at every size
+  return BatchTile{2, 2, 0};
 }
 
 struct TuneTable {

@@ -384,11 +384,12 @@ __device__ inline void static_for(F&& f) {
 // MODE 0: a plain stage follows; 1: the tile's last stage follows (`mid` masks it);
 // 2: this is the tile's last stage.
 template <int WM, bool FP4, int kLoads, int MODE, typename Acc, typename Frag, typename Mid,
-          typename Dma>
+          typename Dma, typename Fix>
 __device__ inline void mfma_stage(Acc (&acc)[WM][WM], uint4 (&aw)[2][WM], uint4 (&bw)[2][WM],
                                   Frag (&af)[2][WM], Frag (&bf)[2][WM], const uint32_t* As,
                                   const uint32_t* Bs, const uint32_t* An, const uint32_t* Bn,
-                                  int arow, int brow, int hsel, Mid&& mid, Dma&& dma) {
+                                  int arow, int brow, int hsel, Mid&& mid, Dma&& dma,
+                                  Fix&& fix) {
   constexpr int kSteps = FP4 ? 4 : 8;  // MFMA k-steps per 128-bit chunk
   constexpr int kT = 2 * kSteps;       // k-steps per stage
   constexpr int kPerStep = (kLoads + kSteps - 1) / kSteps;  // DMA pieces per step, 2nd half
@@ -431,8 +432,14 @@ __device__ inline void mfma_stage(Acc (&acc)[WM][WM], uint4 (&aw)[2][WM], uint4 
   static_for<kT>([&](auto tc) {
     constexpr int t = decltype(tc)::value;
     constexpr int cur = t & 1;
-    if constexpr (t == 0) load_chunk(As, Bs, 1, aw[1], bw[1]);
-    if constexpr (t == kSteps && MODE != 2) load_chunk(An, Bn, 0, aw[0], bw[0]);
+    if constexpr (t == 0) {
+      load_chunk(As, Bs, 1, aw[1], bw[1]);
+      fix(std::integral_constant<int, 0>{}, aw[1], bw[1]);
+    }
+    if constexpr (t == kSteps && MODE != 2) {
+      load_chunk(An, Bn, 0, aw[0], bw[0]);
+      fix(std::integral_constant<int, 1>{}, aw[0], bw[0]);
+    }
     if constexpr (t >= kSteps) {
       // This step's share of the DMA (the stage is one basic block, so the per-step
       // scheduling barrier keeps it within the step).
@@ -514,12 +521,26 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   wait_vmcnt<0>();
   for (int st = 0; st < R; ++st)  // prologue: stages 0 .. R-1
     static_for<kLoads>([&](auto qc) { dma_piece(st, qc); });
-  {
-    // The B panel's K range starts at I0, so its first stage holds S[j][i] for every
-    // pair of the tile: keep the bits with i < j (the related pairs the tile bins) in
-    // LDS for the epilogue, and skip the tile if there are none.
-    wait_vmcnt<(R - 1) * kLoads>();
-    __syncthreads();
+  // The B panel's K range starts at I0, so its first stage holds S[j][i] for every pair of
+  // the tile: each lane takes the relation bits (i < j) of its pairs for the epilogue.
+  // 128-row tiles keep them in registers (no LDS copy, and no tile skip: a tile without a
+  // related pair is rare, and the skip costs a barrier); 256-row tiles, whose registers
+  // are full, keep them in LDS and skip a tile without any.
+  constexpr bool kRelRegs = WM == 2;
+  uint32_t relw[WM][WM];
+  wait_vmcnt<(R - 1) * kLoads>();
+  __syncthreads();
+  if constexpr (kRelRegs) {
+    const uint32_t* Bs0 = ring + kStage;
+    const int32_t dij = clamp_offset(I0 - J0);
+#pragma unroll
+    for (int nb = 0; nb < WM; ++nb)
+#pragma unroll
+      for (int mb = 0; mb < WM; ++mb) {
+        const int br = wc * (WM * 32) + nb * 32 + l32, m = wr * WM + mb;
+        relw[nb][mb] = Bs0[mpos(br, m >> 2) + (m & 3)] & mask_below_d(dij + 32 * m - br);
+      }
+  } else {
     bool any = false;
     const uint32_t* Bs0 = ring + kStage;
     const int32_t dij = clamp_offset(I0 - J0);
@@ -541,10 +562,32 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
     for (int r = threadIdx.x; r < BM; r += kThreads) phis[r] = I0 + r < n ? ta.f.phi[I0 + r] : 0.0;
   }
   // Only the first and the last stage overlap a diagonal block (the A rows' block lies
-  // in stage 0, the B rows' block in the last stage); both are masked in LDS before they
-  // are read, the first here, the last halfway through the stage before it.
-  mask_stage<BM>(ring, ring + kStage, kbeg, I0, J0);
-  __syncthreads();
+  // in stage 0, the B rows' block in the last stage).  128-row tiles mask the operand
+  // words in registers as they read them (no LDS pass and no barrier for it); 256-row
+  // tiles, whose registers are full, mask both stages in LDS before they are read, the
+  // first here, the last halfway through the stage before it.
+  constexpr bool kRegMasks = WM == 2;
+  if constexpr (!kRegMasks) {
+    mask_stage<BM>(ring, ring + kStage, kbeg, I0, J0);
+    __syncthreads();
+  }
+  // Triangular masks on operand words in registers, as they are read: A rows
+  // (i = I0 + row) keep k > i on stage 0, B rows (j = J0 + row) keep k < j on the last
+  // stage; word q of this lane's chunk c of stage s holds k = kbeg + 512 s + 128 c + 32 q + b.
+  auto mask_a = [&](uint4& v, int row, int64_t kw) {
+    const int32_t d = clamp_offset(kw - (I0 + row));
+    v.x &= mask_above_d(d);
+    v.y &= mask_above_d(d + 32);
+    v.z &= mask_above_d(d + 64);
+    v.w &= mask_above_d(d + 96);
+  };
+  auto mask_b = [&](uint4& v, int row, int64_t kw) {
+    const int32_t d = clamp_offset(kw - (J0 + row));
+    v.x &= mask_below_d(d);
+    v.y &= mask_below_d(d + 32);
+    v.z &= mask_below_d(d + 64);
+    v.w &= mask_below_d(d + 96);
+  };
 
   using Frag = typename std::conditional<FP4, v8i, v4i>::type;
   const int arow = wr * WM * 32 + l32, brow = wc * WM * 32 + l32;
@@ -555,6 +598,14 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
 #pragma unroll
   for (int nb = 0; nb < WM; ++nb)
     bw[0][nb] = *(const uint4*)(ring + kStage + mpos(brow + nb * 32, 2 * hsel));
+  if constexpr (kRegMasks) {
+    const int64_t kw = kbeg + 128 * (2 * hsel);  // stage 0, this lane's chunk 0
+#pragma unroll
+    for (int mb = 0; mb < WM; ++mb) mask_a(aw[0][mb], arow + mb * 32, kw);
+    if (nst == 1)
+#pragma unroll
+      for (int nb = 0; nb < WM; ++nb) mask_b(bw[0][nb], brow + nb * 32, kw);
+  }
 #pragma unroll
   for (int mb = 0; mb < WM; ++mb) {
     if constexpr (FP4) af[0][mb] = unpack_fp4_class<0>(aw[0][mb]);
@@ -593,15 +644,31 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
     auto mid = [&]() {
       if constexpr (MODE != 2) wait_vmcnt<(R - 2) * kLoads>();  // stage s+1 has landed
       __syncthreads();
-      if constexpr (MODE == 1) {
+      if constexpr (MODE == 1 && !kRegMasks) {
         mask_stage<BM>(ring + ((s + 1) % R) * 2 * kStage, ring + ((s + 1) % R) * 2 * kStage + kStage,
                        kbeg + (int64_t)(s + 1) * kMStageBits, I0, J0);
         __syncthreads();
       }
     };
+    // which 0: this stage's chunk 1 (A mask on stage 0, B mask on the last stage);
+    // which 1: the next stage's chunk 0 (B mask when it is the last).
+    auto fix = [&](auto whichc, uint4 (&a)[WM], uint4 (&b)[WM]) {
+      constexpr int which = decltype(whichc)::value;
+      if constexpr (!kRegMasks) return;
+      const int64_t kw = kbeg + (int64_t)(s + which) * kMStageBits + 128 * (2 * hsel + 1 - which);
+      if constexpr (which == 0) {
+        if (s == 0)
+#pragma unroll
+          for (int mb = 0; mb < WM; ++mb) mask_a(a[mb], arow + mb * 32, kw);
+      }
+      if constexpr ((which == 0 && MODE == 2) || (which == 1 && MODE == 1)) {
+#pragma unroll
+        for (int nb = 0; nb < WM; ++nb) mask_b(b[nb], brow + nb * 32, kw);
+      }
+    };
     auto dma = [&](auto qc) { dma_piece(s + R, qc); };  // refills this stage's slot
     mfma_stage<WM, FP4, kLoads, MODE>(acc, aw, bw, af, bf, As, As + kStage, An, An + kStage, arow,
-                                      brow, hsel, mid, dma);
+                                      brow, hsel, mid, dma, fix);
   };
   int s = 0;
   for (; s + 2 < nst; ++s) stage(std::integral_constant<int, 0>{}, s);
@@ -624,7 +691,7 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   for (int nb = 0; nb < WM; ++nb) {
 #pragma unroll
     for (int mb = 0; mb < WM; ++mb) {
-      const uint32_t w = rel[((wave * WM + nb) * WM + mb) * 32 + l32] >> (4 * hsel);
+      const uint32_t w = (kRelRegs ? relw[nb][mb] : rel[((wave * WM + nb) * WM + mb) * 32 + l32]) >> (4 * hsel);
       if (!__ballot(w != 0u)) continue;  // no related pair in this 32x32 block
       const int32_t wn = (int32_t)~w;
       uint32_t big = 0;  // max over the block of key + 1 (0 for unrelated pairs)
@@ -668,7 +735,7 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
       bool any = false;
 #pragma unroll
       for (int nb = 0; nb < WM; ++nb) {
-        const uint32_t w = rel[((wave * WM + nb) * WM + mb) * 32 + l32] >> (4 * hsel);
+        const uint32_t w = (kRelRegs ? relw[nb][mb] : rel[((wave * WM + nb) * WM + mb) * 32 + l32]) >> (4 * hsel);
         any |= w != 0u;
         wn[nb] = (int32_t)~w;
       }
@@ -1072,7 +1139,8 @@ __device__ inline int xcc_id() {
 template <int BM, int HB>
 struct MfmaLds {
   uint32_t ring[MRing<BM>::value * 2 * BM * kMStageU32] __attribute__((aligned(16)));
-  uint32_t rel[BM * BM / 32];  // relation bits of the current tile's pairs (i < j)
+  uint32_t rel[BM == 128 ? 1 : BM * BM / 32];  // relation bits of the tile's pairs (i < j);
+                                              // 128-row tiles keep theirs in registers
   double phis[BM + 8];         // phi of the tile's rows, then c_0 .. c_3, 0 (d'Alembertian)
   uint32_t hist[HB + 64];      // bins, then one spare word per lane (never flushed)
   uint32_t maxbin;

@@ -365,11 +365,28 @@ template <int N, typename F>
 __device__ inline void static_for(F&& f) {
   static_for_seq(f, std::make_integer_sequence<int, N>{});
 }
+// f(std::integral_constant<int, i>) for i = A .. B-1.
+template <int A, typename F, int... I>
+__device__ inline void static_for_from(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, A + I>{}), ...);
+}
+template <int A, int B, typename F>
+__device__ inline void static_for_range(F&& f) {
+  static_for_from<A>(f, std::make_integer_sequence<int, B - A>{});
+}
+
+// Chunk (of four per stage row) that half-wave hsel multiplies in half cc of a stage.
+template <int WM>
+__device__ inline int mchunk(int hsel, int cc) { return WM == 2 ? hsel + 2 * cc : 2 * hsel + cc; }
 
 // One stage (512 bits of K = 4 chunks of 128) as a flat, software-pipelined sequence of
-// k-steps.  Lanes 0-31 take chunks 0 and 1 of every row, lanes 32-63 chunks 2 and 3:
-// the MFMA's K order only has to be the same for A and B, and with this assignment
-// each half-wave reads just the chunks it multiplies.  A chunk gives 4 fp4 k-steps
+// k-steps.  Each half-wave multiplies two chunks of every row, its first in the stage's
+// first half of k-steps and its second in the second half: with 256-row tiles lanes 0-31
+// take chunks 0 and 1 and lanes 32-63 chunks 2 and 3; with 128-row tiles lanes 0-31 take
+// chunks 0 and 2 and lanes 32-63 chunks 1 and 3, so the first half covers bits 0-255 of
+// the stage and a last stage whose K range ends by bit 256 (`half`) skips the second half,
+// whose B operands are masked to zero.  The MFMA's K order only has to be the same for A
+// and B, and with either assignment each half-wave reads just the chunks it multiplies.  A chunk gives 4 fp4 k-steps
 // (one per bit class) or 8 int8 k-steps (word w, nibble e of every byte: bits
 // 32w + 4e + q + 8b in byte b of register q).  The operands of step t+1 are unpacked
 // while the MFMAs of step t issue, and the scheduler is told to interleave them (one
@@ -388,18 +405,18 @@ template <int WM, bool FP4, int kLoads, int MODE, typename Acc, typename Frag, t
 __device__ inline void mfma_stage(Acc (&acc)[WM][WM], uint4 (&aw)[2][WM], uint4 (&bw)[2][WM],
                                   Frag (&af)[2][WM], Frag (&bf)[2][WM], const uint32_t* As,
                                   const uint32_t* Bs, const uint32_t* An, const uint32_t* Bn,
-                                  int arow, int brow, int hsel, Mid&& mid, Dma&& dma,
-                                  Fix&& fix) {
+                                  int arow, int brow, int hsel, bool half, Mid&& mid,
+                                  Dma&& dma, Fix&& fix) {
   constexpr int kSteps = FP4 ? 4 : 8;  // MFMA k-steps per 128-bit chunk
   constexpr int kT = 2 * kSteps;       // k-steps per stage
   constexpr int kPerStep = (kLoads + kSteps - 1) / kSteps;  // DMA pieces per step, 2nd half
-  const int c0 = 2 * hsel;             // this half-wave's first chunk
   auto load_chunk = [&](const uint32_t* A, const uint32_t* B, int cc, uint4 (&a)[WM],
                         uint4 (&b)[WM]) {
+    const int c = mchunk<WM>(hsel, cc);
 #pragma unroll
-    for (int mb = 0; mb < WM; ++mb) a[mb] = *(const uint4*)(A + mpos(arow + mb * 32, c0 + cc));
+    for (int mb = 0; mb < WM; ++mb) a[mb] = *(const uint4*)(A + mpos(arow + mb * 32, c));
 #pragma unroll
-    for (int nb = 0; nb < WM; ++nb) b[nb] = *(const uint4*)(B + mpos(brow + nb * 32, c0 + cc));
+    for (int nb = 0; nb < WM; ++nb) b[nb] = *(const uint4*)(B + mpos(brow + nb * 32, c));
   };
   auto unpack_step = [&](auto step, int cc, Frag (&fa)[WM], Frag (&fb)[WM]) {
     constexpr int u = decltype(step)::value;  // step within the chunk
@@ -429,7 +446,7 @@ __device__ inline void mfma_stage(Acc (&acc)[WM][WM], uint4 (&aw)[2][WM], uint4 
         }
       }
   };
-  static_for<kT>([&](auto tc) {
+  auto step = [&](auto tc) {
     constexpr int t = decltype(tc)::value;
     constexpr int cur = t & 1;
     if constexpr (t == 0) {
@@ -467,7 +484,9 @@ __device__ inline void mfma_stage(Acc (&acc)[WM][WM], uint4 (&aw)[2][WM], uint4 
     // update the same accumulators and must not be placed back to back.
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (t == kSteps - 1) mid();
-  });
+  };
+  static_for_range<0, kSteps>(step);
+  if (MODE != 2 || !half) static_for_range<kSteps, kT>(step);
 }
 
 // EPI 0: histogram of the interval sizes of the related pairs.  EPI 1: d'Alembertian
@@ -594,12 +613,13 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   uint4 aw[2][WM], bw[2][WM];
   Frag af[2][WM], bf[2][WM];
 #pragma unroll
-  for (int mb = 0; mb < WM; ++mb) aw[0][mb] = *(const uint4*)(ring + mpos(arow + mb * 32, 2 * hsel));
+  for (int mb = 0; mb < WM; ++mb)
+    aw[0][mb] = *(const uint4*)(ring + mpos(arow + mb * 32, mchunk<WM>(hsel, 0)));
 #pragma unroll
   for (int nb = 0; nb < WM; ++nb)
-    bw[0][nb] = *(const uint4*)(ring + kStage + mpos(brow + nb * 32, 2 * hsel));
+    bw[0][nb] = *(const uint4*)(ring + kStage + mpos(brow + nb * 32, mchunk<WM>(hsel, 0)));
   if constexpr (kRegMasks) {
-    const int64_t kw = kbeg + 128 * (2 * hsel);  // stage 0, this lane's chunk 0
+    const int64_t kw = kbeg + 128 * mchunk<WM>(hsel, 0);  // stage 0, this lane's first chunk
 #pragma unroll
     for (int mb = 0; mb < WM; ++mb) mask_a(aw[0][mb], arow + mb * 32, kw);
     if (nst == 1)
@@ -650,12 +670,12 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
         __syncthreads();
       }
     };
-    // which 0: this stage's chunk 1 (A mask on stage 0, B mask on the last stage);
-    // which 1: the next stage's chunk 0 (B mask when it is the last).
+    // which 0: this stage's second chunk (A mask on stage 0, B mask on the last stage);
+    // which 1: the next stage's first chunk (B mask when it is the last).
     auto fix = [&](auto whichc, uint4 (&a)[WM], uint4 (&b)[WM]) {
       constexpr int which = decltype(whichc)::value;
       if constexpr (!kRegMasks) return;
-      const int64_t kw = kbeg + (int64_t)(s + which) * kMStageBits + 128 * (2 * hsel + 1 - which);
+      const int64_t kw = kbeg + (int64_t)(s + which) * kMStageBits + 128 * mchunk<WM>(hsel, 1 - which);
       if constexpr (which == 0) {
         if (s == 0)
 #pragma unroll
@@ -667,8 +687,10 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
       }
     };
     auto dma = [&](auto qc) { dma_piece(s + R, qc); };  // refills this stage's slot
+    // a last stage whose K range ends by its bit 256 skips its second half (128-row tiles)
+    const bool half = WM == 2 && MODE == 2 && kend - (kbeg + (int64_t)s * kMStageBits) <= 256;
     mfma_stage<WM, FP4, kLoads, MODE>(acc, aw, bw, af, bf, As, As + kStage, An, An + kStage, arow,
-                                      brow, hsel, mid, dma, fix);
+                                      brow, hsel, half, mid, dma, fix);
   };
   int s = 0;
   for (; s + 2 < nst; ++s) stage(std::integral_constant<int, 0>{}, s);

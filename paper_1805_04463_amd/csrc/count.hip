@@ -489,6 +489,17 @@ __device__ inline void mfma_stage(Acc (&acc)[WM][WM], uint4 (&aw)[2][WM], uint4 
   if (MODE != 2 || !half) static_for_range<kSteps, kT>(step);
 }
 
+// Tiles of one ensemble row panel run one after another in a workgroup (J descending):
+// the last stage of a 128-row tile fetches the next tile's first stage into the ring slot
+// it leaves free, and the barrier at that stage's middle publishes it, so the next tile
+// starts without a barrier or a wait.  rofs: the ring slot of the tile's stage 0; ready:
+// that stage is in place; next_j0: the next tile's first column, or -1.
+struct TileChain {
+  int rofs = 0;
+  bool ready = false;
+  int64_t next_j0 = -1;
+};
+
 // EPI 0: histogram of the interval sizes of the related pairs.  EPI 1: d'Alembertian
 // sums, per column j, of c_m phi(i) over the related pairs (i, j) with m interior elements.
 // FITS: every count is below HB (instances of at most HB + 1 points), so the epilogue
@@ -496,7 +507,8 @@ __device__ inline void mfma_stage(Acc (&acc)[WM][WM], uint4 (&aw)[2][WM], uint4 
 template <int WM, int HB, bool FP4 = false, int EPI = 0, bool FITS = false>
 __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& ta, uint32_t* ring,
                                                                 uint32_t* rel, uint32_t* lds_hist,
-                                                                uint32_t& tmax, double* phis) {
+                                                                uint32_t& tmax, double* phis,
+                                                                TileChain& chain) {
   using Acc = typename std::conditional<FP4, v16f, v16i>::type;
   constexpr int BM = 2 * WM * 32;
   constexpr int kStage = BM * kMStageU32;      // one panel stage, uint32 words
@@ -523,13 +535,18 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   // LDS byte address of the ring (the low 32 bits of a generic LDS pointer).
   const uint32_t ring_addr = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)ring);
   constexpr int R = MRing<BM>::value;
+  constexpr bool kChain = WM == 2;  // 128-row tiles (two ring slots) chain their first stages
+  const int rofs = kChain ? chain.rofs : 0;
+  const bool ready = kChain && chain.ready;
+  const bool fetch_next = kChain && chain.next_j0 >= 0;
+  auto slot_of = [&](int st) { return (st + rofs) % R; };
   // DMA of stage st into its ring slot; past the last stage the requests are pushed out
   // of the descriptors' range (panels are below 1 GiB), so they read nothing.  Issuing
   // them anyway keeps the stage code free of branches, which would let the compiler
   // gather all requests in one place.
   auto dma_piece = [&](int st, auto qc) {
     constexpr int q = decltype(qc)::value;
-    const uint32_t slot = ring_addr + (st % R) * 2 * kStage * 4;
+    const uint32_t slot = ring_addr + slot_of(st) * 2 * kStage * 4;
     const int32_t kb = st < nst ? kbyte0 + st * (kMStageBits / 8) : (int32_t)0x40000000;
     constexpr int qp = q < kPer ? q : q - kPer;  // request within its panel
     if constexpr (q < kPer) dma_one<BM>(ra, slot, vbase, kb + qp * rows64, q);
@@ -538,7 +555,7 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   // The previous tile's global histogram atomics: retiring them here leaves the compiler
   // no outstanding memory operation to wait for inside the stage loop.
   wait_vmcnt<0>();
-  for (int st = 0; st < R; ++st)  // prologue: stages 0 .. R-1
+  for (int st = ready ? 1 : 0; st < R; ++st)  // prologue: stages 0 (unless in place) .. R-1
     static_for<kLoads>([&](auto qc) { dma_piece(st, qc); });
   // The B panel's K range starts at I0, so its first stage holds S[j][i] for every pair of
   // the tile: each lane takes the relation bits (i < j) of its pairs for the epilogue.
@@ -547,10 +564,13 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   // are full, keep them in LDS and skip a tile without any.
   constexpr bool kRelRegs = WM == 2;
   uint32_t relw[WM][WM];
-  wait_vmcnt<(R - 1) * kLoads>();
-  __syncthreads();
+  uint32_t* const ring0 = ring + slot_of(0) * 2 * kStage;  // stage 0: A, then B
+  if (!ready) {
+    wait_vmcnt<(R - 1) * kLoads>();
+    __syncthreads();
+  }
   if constexpr (kRelRegs) {
-    const uint32_t* Bs0 = ring + kStage;
+    const uint32_t* Bs0 = ring0 + kStage;
     const int32_t dij = clamp_offset(I0 - J0);
 #pragma unroll
     for (int nb = 0; nb < WM; ++nb)
@@ -561,7 +581,7 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
       }
   } else {
     bool any = false;
-    const uint32_t* Bs0 = ring + kStage;
+    const uint32_t* Bs0 = ring0 + kStage;
     const int32_t dij = clamp_offset(I0 - J0);
 #pragma unroll
     for (int nb = 0; nb < WM; ++nb)
@@ -587,7 +607,7 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   // first here, the last halfway through the stage before it.
   constexpr bool kRegMasks = WM == 2;
   if constexpr (!kRegMasks) {
-    mask_stage<BM>(ring, ring + kStage, kbeg, I0, J0);
+    mask_stage<BM>(ring0, ring0 + kStage, kbeg, I0, J0);
     __syncthreads();
   }
   // Triangular masks on operand words in registers, as they are read: A rows
@@ -614,10 +634,10 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   Frag af[2][WM], bf[2][WM];
 #pragma unroll
   for (int mb = 0; mb < WM; ++mb)
-    aw[0][mb] = *(const uint4*)(ring + mpos(arow + mb * 32, mchunk<WM>(hsel, 0)));
+    aw[0][mb] = *(const uint4*)(ring0 + mpos(arow + mb * 32, mchunk<WM>(hsel, 0)));
 #pragma unroll
   for (int nb = 0; nb < WM; ++nb)
-    bw[0][nb] = *(const uint4*)(ring + kStage + mpos(brow + nb * 32, mchunk<WM>(hsel, 0)));
+    bw[0][nb] = *(const uint4*)(ring0 + kStage + mpos(brow + nb * 32, mchunk<WM>(hsel, 0)));
   if constexpr (kRegMasks) {
     const int64_t kw = kbeg + 128 * mchunk<WM>(hsel, 0);  // stage 0, this lane's first chunk
 #pragma unroll
@@ -659,13 +679,14 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
 
   auto stage = [&](auto modec, int s) {
     constexpr int MODE = decltype(modec)::value;
-    const uint32_t* As = ring + (s % R) * 2 * kStage;
-    const uint32_t* An = ring + ((s + 1) % R) * 2 * kStage;
+    const uint32_t* As = ring + slot_of(s) * 2 * kStage;
+    const uint32_t* An = ring + slot_of(s + 1) * 2 * kStage;
     auto mid = [&]() {
       if constexpr (MODE != 2) wait_vmcnt<(R - 2) * kLoads>();  // stage s+1 has landed
+      else if (fetch_next) wait_vmcnt<0>();  // the next tile's first stage has landed
       __syncthreads();
       if constexpr (MODE == 1 && !kRegMasks) {
-        mask_stage<BM>(ring + ((s + 1) % R) * 2 * kStage, ring + ((s + 1) % R) * 2 * kStage + kStage,
+        mask_stage<BM>(ring + slot_of(s + 1) * 2 * kStage, ring + slot_of(s + 1) * 2 * kStage + kStage,
                        kbeg + (int64_t)(s + 1) * kMStageBits, I0, J0);
         __syncthreads();
       }
@@ -689,6 +710,21 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
     auto dma = [&](auto qc) { dma_piece(s + R, qc); };  // refills this stage's slot
     // a last stage whose K range ends by its bit 256 skips its second half (128-row tiles)
     const bool half = WM == 2 && MODE == 2 && kend - (kbeg + (int64_t)s * kMStageBits) <= 256;
+    if constexpr (MODE == 2 && kChain) {
+      // The next tile's first stage (same A rows and K range, B rows from next_j0) into the
+      // slot after this one, free since the previous stage's middle.
+      if (fetch_next) {
+        const __amdgpu_buffer_rsrc_t rbn =
+            uniform_rsrc(ta.S32 + chain.next_j0 * ta.ld32, (uint32_t)(BM * ld * 8));
+        const uint32_t slot = ring_addr + slot_of(s + 1) * 2 * kStage * 4;
+        static_for<kLoads>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          constexpr int qp = q < kPer ? q : q - kPer;
+          if constexpr (q < kPer) dma_one<BM>(ra, slot, vbase, kbyte0 + qp * rows64, q);
+          else dma_one<BM>(rbn, slot + kStage * 4, vbase, kbyte0 + qp * rows64, qp);
+        });
+      }
+    }
     mfma_stage<WM, FP4, kLoads, MODE>(acc, aw, bw, af, bf, As, As + kStage, An, An + kStage, arow,
                                       brow, hsel, half, mid, dma, fix);
   };
@@ -697,6 +733,10 @@ __device__ __attribute__((always_inline)) inline bool mfma_tile(const TileArgs& 
   if (nst >= 2) stage(std::integral_constant<int, 1>{}, s++);
   stage(std::integral_constant<int, 2>{}, s);
   wait_vmcnt<0>();  // the out-of-range requests of the last stages, before the ring is reused
+  if constexpr (kChain) {
+    chain.rofs = slot_of(nst);  // the next tile's stage 0 went to the slot after the last
+    chain.ready = fetch_next;
+  }
 
   if constexpr (EPI == 0) {
   // Epilogue.  32x32 accumulator layout: lane holds column (lane & 31) and rows
@@ -1237,7 +1277,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_count_mfma(const uint64_t* __re
     }
     ta.I0 = I * BM;
     ta.J0 = J * BM;
-    if (mfma_tile<WM, HB, FP4, EPI>(ta, L.ring, L.rel, L.hist, tmax, L.phis))
+    TileChain none;
+    if (mfma_tile<WM, HB, FP4, EPI>(ta, L.ring, L.rel, L.hist, tmax, L.phis, none))
       pairs_in_lds += (int64_t)BM * BM;
   }
   if constexpr (EPI == 0) flush_hist<HB>(L.hist, hist, n - 1, tmax, &L.maxbin);
@@ -1332,13 +1373,15 @@ __global__ __launch_bounds__(kThreads, MODE == 4 ? 1 : 2) void k_count_batch(
     const int64_t I = (int64_t)((it >> 8) & 255u);
     const int64_t T = ceil_div(ta.n, BM);
     ta.I0 = I * BM;
+    TileChain chain;
     for (int64_t J = T - 1; J >= I; --J) {
       ta.J0 = J * BM;
+      chain.next_j0 = J > I ? (J - 1) * BM : -1;
       if constexpr (MODE == 0) {
         if (pair_tile<HB>(ta, L.As, L.Bs, L.pairs, L.hist, tmax, pair_max) == 2)
           bitset_tile<HB>(ta, L.As, L.Bs, L.hist, tmax);
       } else
-        mfma_tile<MODE, HB, FP4, 0, true>(ta, L.ring, L.rel, L.hist, tmax, nullptr);
+        mfma_tile<MODE, HB, FP4, 0, true>(ta, L.ring, L.rel, L.hist, tmax, nullptr, chain);
     }
   }
   if (cur >= 0) flush_hist<HB>(L.hist, ta.hist, ta.n - 1, tmax, &L.maxbin);

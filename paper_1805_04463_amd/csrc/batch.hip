@@ -200,7 +200,7 @@ cs_status build_plan(int64_t count, const int64_t* n, int counter, int n_eps, co
   p->counter = counter;
   p->n_eps = n_eps;
   p->inst.resize(count);
-  std::vector<uint32_t> build;
+  std::vector<std::vector<uint32_t>> bitems(count);  // builder items of each instance
   struct Item {
     uint32_t packed;
     int64_t cost;
@@ -219,9 +219,17 @@ cs_status build_plan(int64_t count, const int64_t* n, int counter, int n_eps, co
     boff += d.n * d.ld;
     hoff += d.n - 1;
     const int64_t nb = ceil_div(d.n, 64);
-    for (int64_t bi = 0; bi < nb; ++bi)
-      for (int64_t bj = bi; bj < nb; ++bj)
-        build.push_back((uint32_t)(k << 16 | bi << 8 | bj));
+    // Builder items (row group g: row blocks kBuildRowBlocks g + r; column block bj) in
+    // patches of kBuildPatch x kBuildPatch blocks: a patch writes whole 128-byte lines of
+    // its rows' words and of its transposed words, so the lines are complete while the
+    // XCD that builds the instance holds them in its L2.
+    constexpr int64_t G = kBuildPatch / kBuildRowBlocks;  // row groups per patch
+    for (int64_t pr = 0; pr * kBuildPatch < nb; ++pr)
+      for (int64_t pc = pr; pc * kBuildPatch < nb; ++pc)
+        for (int64_t g = pr * G; g < pr * G + G && g * kBuildRowBlocks < nb; ++g)
+          for (int64_t bj = std::max(pc * kBuildPatch, g * kBuildRowBlocks);
+               bj < std::min((pc + 1) * kBuildPatch, nb); ++bj)
+            bitems[k].push_back((uint32_t)(k << 16 | g << 8 | bj));
     const int b = bucket_of(d.n);
     const BatchTile cfg = force ? *force
                           : (tune.have[cslot][b] ? tune.cfg[cslot][b] : default_tile(counter, d.n));
@@ -241,6 +249,32 @@ cs_status build_plan(int64_t count, const int64_t* n, int counter, int n_eps, co
   p->coords_len = coff;
   p->bits_len = boff;
   p->hist_len = hoff;
+  // Builder lists, one per XCD: whole instances dealt largest first to the shortest list,
+  // so that every line of a matrix is written from one L2 (partial lines written back
+  // from several XCDs multiplied the builder's HBM writes).  Workgroup b takes list
+  // b mod 8 (the XCD that the dispatcher gives it), entries kBuildWaves (b div 8) + wave;
+  // lists are padded with kNoBuildItem to one length, a multiple of kBuildWaves.
+  std::vector<uint32_t> build;
+  {
+    std::vector<int64_t> order(count);
+    for (int64_t k = 0; k < count; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+      return bitems[a].size() > bitems[b].size();
+    });
+    std::vector<uint32_t> lists[kBatchQueues];
+    for (int64_t k : order) {
+      int best = 0;
+      for (int x = 1; x < kBatchQueues; ++x)
+        if (lists[x].size() < lists[best].size()) best = x;
+      lists[best].insert(lists[best].end(), bitems[k].begin(), bitems[k].end());
+    }
+    size_t len = 0;
+    for (auto& l : lists) len = std::max(len, l.size());
+    len = (len + kBuildWaves - 1) / kBuildWaves * kBuildWaves;
+    build.assign(len * kBatchQueues, kNoBuildItem);
+    for (int x = 0; x < kBatchQueues; ++x)
+      std::copy(lists[x].begin(), lists[x].end(), build.begin() + x * len);
+  }
   p->n_build = (int64_t)build.size();
   for (int s = 0; s < p->nslots; ++s) {
     // One queue per XCD holding whole instances, dealt largest first to the least loaded

@@ -9,7 +9,9 @@
 // block bj.  A 64x64 bit transpose across the wave (six butterfly stages of lane
 // shuffles) turns those row words into the words of rows j for column block bi, so each
 // unordered pair is tested once and both halves of the symmetric matrix are written.
-// Workgroups walk 1024 x 1024-point patches, one XCD per patch (k_build).
+// Workgroups walk 1024 x 1024-point patches, one XCD per patch (k_build).  The ensemble
+// builder gives each wave several row blocks against one column block, so that each
+// column point read from LDS serves several rows of a lane.
 //
 // Arithmetic: fp64, in the order written, no contraction (built with
 // -ffp-contract=off and explicit round-to-nearest intrinsics); on CDNA4 fp64 VALU
@@ -128,6 +130,36 @@ __device__ inline bool later_precedes(const Pt<CS_MINK3_DIAMOND>& a,
   return __dmul_rn(dt, dt) > __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
 }
 
+// The wave's lane mask of later_precedes(a, b).  Where the relation is the AND of two
+// compares, each compare writes its lane mask to scalar registers and the masks are
+// ANDed there: a ballot of the AND would first turn it into a per-lane value and back
+// (two VALU instructions more per pair test).  fcmp predicate 4 is ordered less-than,
+// false for NaN like the C operator.
+template <int R>
+__device__ inline uint64_t precedes_mask(const Pt<R>& a, const Pt<R>& b) {
+  return __builtin_amdgcn_ballot_w64(later_precedes(a, b));
+}
+template <>
+__device__ inline uint64_t precedes_mask(const Pt<CS_MINK2_DIAMOND>& a,
+                                         const Pt<CS_MINK2_DIAMOND>& b) {
+  return __builtin_amdgcn_fcmp(a.u, b.u, 4) & __builtin_amdgcn_fcmp(a.v, b.v, 4);
+}
+template <>
+__device__ inline uint64_t precedes_mask(const Pt<CS_DS4_SLAB>& a, const Pt<CS_DS4_SLAB>& b) {
+  double cd = __dadd_rn(__dmul_rn(a.c, b.c), __dmul_rn(a.s, b.s));
+  double dot = __dadd_rn(__dmul_rn(a.n0, b.n0), __dmul_rn(a.n1, b.n1));
+  dot = __dadd_rn(dot, __dmul_rn(a.n2, b.n2));
+  dot = __dadd_rn(dot, __dmul_rn(a.n3, b.n3));
+  return __builtin_amdgcn_fcmp(a.x, b.x, 4) & __builtin_amdgcn_fcmp(cd, dot, 4);
+}
+template <>
+__device__ inline uint64_t precedes_mask(const Pt<CS_DS2_SLAB>& a, const Pt<CS_DS2_SLAB>& b) {
+  const double pi = 3.141592653589793;
+  double dth = fabs(__dsub_rn(a.th, b.th));
+  dth = __dsub_rn(pi, fabs(__dsub_rn(pi, dth)));
+  return __builtin_amdgcn_fcmp(a.eta, b.eta, 4) & __builtin_amdgcn_fcmp(dth, __dsub_rn(b.eta, a.eta), 4);
+}
+
 // 2 w + (this lane's bit of the wave mask m): one add with m as the carry-in.
 __device__ inline uint32_t shift_in(uint32_t w, uint64_t m) {
   uint32_t r;
@@ -158,74 +190,98 @@ __device__ inline uint64_t wave_transpose64(uint64_t x) {
   return x;
 }
 
-// Row word of lane l for the 64 column points j0 .. j0+63: bit c is column c.  Columns
-// enter from the top, 63 first, each compare's wave mask shifted in as a carry.  The
-// columns are wave-uniform.  In the 3+1 and 2+1 diamonds they come through scalar loads
-// into SGPRs and feed the fp64 operations directly, instead of broadcast reads from LDS
-// (16 bytes per lane per instruction: the LDS bound of those blocks).  The other regions
+// Row words of lane l for the 64 column points j0 .. j0+63, one per row point pi[r]:
+// bit c is column c.  Columns enter from the top, 63 first, each compare's wave mask
+// shifted in as a carry.  The columns are wave-uniform, and each is read once for all RB
+// rows of the lane.  In the 3+1 and 2+1 diamonds they come through scalar loads into
+// SGPRs and feed the fp64 operations directly, instead of broadcast reads from LDS (16
+// bytes per lane per instruction: the LDS bound of those blocks).  The other regions
 // stage them in LDS: the 7-plane de Sitter slab's columns, loaded ahead, do not fit the
 // scalar registers, and the two-plane predicates are too short to hide the scalar load
-// latency (both measured slower).  A block that ends past n repeats point n-1 for the
-// missing columns (masked off by the caller).
+// latency (both measured slower); with several rows per lane a broadcast read serves RB
+// rows.  A block that ends past n repeats point n-1 for the missing columns (masked off
+// by the caller).
 template <int R>
 constexpr bool kScalarColumns = R == CS_MINK4_DIAMOND || R == CS_MINK3_DIAMOND;
 
-template <int R, bool FULL>
-__device__ __attribute__((always_inline)) inline uint64_t row_word(
-    const double* __restrict__ coords, int64_t n, int64_t j0, const Pt<R>& pi, Pt<R>* cols) {
+template <int R, bool FULL, int RB>
+__device__ __attribute__((always_inline)) inline void row_words(
+    const double* __restrict__ coords, int64_t n, int64_t j0, const Pt<R> (&pi)[RB], Pt<R>* cols,
+    uint64_t (&out)[RB]) {
   if constexpr (!kScalarColumns<R>) {
     const int lane = threadIdx.x & 63;
     cols[lane] = load_pt(coords, n, j0 + lane < n ? j0 + lane : n - 1, (Pt<R>*)nullptr);
     __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the wave's LDS writes have landed
     __builtin_amdgcn_wave_barrier();
   }
-  uint32_t half[2];
+  uint32_t half[RB][2];
 #pragma unroll
   for (int h = 1; h >= 0; --h) {
-    uint32_t w = 0;
+    uint32_t w[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) w[r] = 0;
 #pragma unroll
     for (int c = 31; c >= 0; --c) {
       int64_t j = j0 + 32 * h + c;
       if (!FULL) j = j < n ? j : n - 1;
       const Pt<R> q = kScalarColumns<R> ? load_pt(coords, n, j, (Pt<R>*)nullptr) : cols[32 * h + c];
-      w = shift_in(w, __builtin_amdgcn_ballot_w64(later_precedes(pi, q)));
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        w[r] = shift_in(w[r], precedes_mask(pi[r], q));
     }
-    half[h] = w;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) half[r][h] = w[r];
   }
   if constexpr (!kScalarColumns<R>) __builtin_amdgcn_wave_barrier();
-  return ((uint64_t)half[1] << 32) | half[0];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) out[r] = ((uint64_t)half[r][1] << 32) | half[r][0];
 }
 
-// One wave: the 64x64 block (bi, bj), bi <= bj, of an n-point matrix S with stride ld;
-// bi and bj are wave-uniform.  Lane l owns row i = 64 bi + l and collects its row word
-// for the 64 column points of block bj.  The transposed words (rows of block bj, columns
-// of block bi) come from one 64x64 bit transpose of the row words, so each unordered
-// pair is tested once.  The wave owning the last column block of a row block also
-// zeroes that row block's padding words [nb, ld), so every word of S is written exactly
-// once.
-template <int R>
+// One wave: the 64x64 blocks (bi0 + r, bj), r = 0 .. RB-1, of an n-point matrix S with
+// stride ld, those with bi0 + r <= bj (bi0 <= bj; bi0 and bj are wave-uniform).  Lane l
+// owns rows i = 64 (bi0 + r) + l and collects their row words for the 64 column points
+// of block bj.  The transposed words (rows of block bj, columns of block bi0 + r) come
+// from a 64x64 bit transpose of each row word, so each unordered pair is tested once.
+// Row blocks below the diagonal (bi0 + r > bj) are tested but not written.  The wave
+// owning the last column block of a row block also zeroes that row block's padding words
+// [nb, ld), so every word of S is written exactly once.
+template <int R, int RB>
 __device__ __attribute__((always_inline)) inline void build_block(
     const double* __restrict__ coords, int64_t n, uint64_t* __restrict__ S, int64_t ld, int64_t nb,
-    int64_t bi, int64_t bj, Pt<R>* cols) {
+    int64_t bi0, int64_t bj, Pt<R>* cols) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = bi * 64 + lane, j = bj * 64 + lane;
-  const bool iv = i < n, jv = j < n;
-  const Pt<R> pi = load_pt(coords, n, iv ? i : n - 1, (Pt<R>*)nullptr);
-  uint64_t row = bj * 64 + 64 <= n ? row_word<R, true>(coords, n, bj * 64, pi, cols)
-                                   : row_word<R, false>(coords, n, bj * 64, pi, cols);
-  const int64_t ncols = n - bj * 64;  // valid columns of this block (>= 1)
-  if (ncols < 64) row &= (1ull << ncols) - 1ull;
-  if (bi == bj) row &= lane == 63 ? 0ull : (~0ull << (lane + 1));  // only j > i
-  if (!iv) row = 0;
-  const uint64_t col = wave_transpose64(row);  // lane l: row j's bits for columns of bi
-  if (bi == bj) {
-    if (iv) S[i * ld + bi] = row | col;
-  } else {
-    if (iv) S[i * ld + bj] = row;
-    if (jv) S[j * ld + bi] = col;
+  Pt<R> pi[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const int64_t i = (bi0 + r) * 64 + lane;
+    pi[r] = load_pt(coords, n, i < n ? i : n - 1, (Pt<R>*)nullptr);
   }
-  if (bj == nb - 1 && iv)
-    for (int64_t w = nb; w < ld; ++w) S[i * ld + w] = 0;
+  uint64_t rows[RB];
+  if (bj * 64 + 64 <= n) row_words<R, true, RB>(coords, n, bj * 64, pi, cols, rows);
+  else row_words<R, false, RB>(coords, n, bj * 64, pi, cols, rows);
+  const int64_t j = bj * 64 + lane;
+  const bool jv = j < n;
+  const int64_t ncols = n - bj * 64;  // valid columns of this block (>= 1)
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const int64_t bi = bi0 + r;
+    if (bi > bj) break;  // this and the later row blocks lie below the diagonal
+    const int64_t i = bi * 64 + lane;
+    const bool iv = i < n;
+    uint64_t row = rows[r];
+    if (ncols < 64) row &= (1ull << ncols) - 1ull;
+    if (bi == bj) row &= lane == 63 ? 0ull : (~0ull << (lane + 1));  // only j > i
+    if (!iv) row = 0;
+    const uint64_t col = wave_transpose64(row);  // lane l: row j's bits for columns of bi
+    if (bi == bj) {
+      if (iv) S[i * ld + bi] = row | col;
+    } else {
+      if (iv) S[i * ld + bj] = row;
+      if (jv) S[j * ld + bi] = col;
+    }
+    if (bj == nb - 1 && iv)
+      for (int64_t w = nb; w < ld; ++w) S[i * ld + w] = 0;
+  }
 }
 
 // Patches of 16 x 16 blocks (1024 x 1024 points) of the upper triangle, 64 workgroups
@@ -266,23 +322,31 @@ __global__ __launch_bounds__(256) void k_build(const double* __restrict__ coords
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t bj = (px * kGroups + l % kGroups) * kWavesPerBlock + wave;
   if (bi >= nb || bj >= nb || bj < bi) return;  // wave-uniform exit; no block barriers below
-  build_block<R>(coords, n, S, ld, nb, bi, bj, cols[kScalarColumns<R> ? 0 : wave]);
+  build_block<R, 1>(coords, n, S, ld, nb, bi, bj, cols[kScalarColumns<R> ? 0 : wave]);
 }
 
-// Ensemble of 1+1 diamonds: wave w of block b takes work item 4b + w, packed as
-// instance << 16 | bi << 8 | bj.
+// Ensemble of 1+1 diamonds.  Work items are packed as instance << 16 | g << 8 | bj: row
+// blocks kBuildRowBlocks g + r against column block bj >= kBuildRowBlocks g.  Each
+// column point read from LDS serves kBuildRowBlocks rows of the lane, which takes the
+// blocks off the LDS bound of one row per lane.  The items form kBatchQueues lists of
+// equal length (one per XCD, padded with kNoBuildItem); wave w of workgroup b takes
+// entry kBuildWaves (b div kBatchQueues) + w of list b mod kBatchQueues.
+static_assert(kWavesPerBlock == kBuildWaves, "ensemble builder lists are dealt per workgroup");
 __global__ __launch_bounds__(256) void k_build_batch(const double* __restrict__ coords,
                                                      const BatchInst* __restrict__ inst,
                                                      const uint32_t* __restrict__ items,
                                                      int64_t nitems, uint64_t* __restrict__ bits) {
   __shared__ Pt<CS_MINK2_DIAMOND> cols[kWavesPerBlock][64];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-  if (t >= nitems) return;
+  const int64_t per_list = nitems / kBatchQueues;
+  const int64_t t = (int64_t)(blockIdx.x % kBatchQueues) * per_list +
+                    (int64_t)(blockIdx.x / kBatchQueues) * kWavesPerBlock + wave;
   const uint32_t it = items[t];
+  if (it == kNoBuildItem) return;
   const BatchInst d = inst[it >> 16];
-  build_block<CS_MINK2_DIAMOND>(coords + d.coord_off, d.n, bits + d.bits_off, d.ld,
-                                ceil_div(d.n, 64), (it >> 8) & 255u, it & 255u, cols[wave]);
+  build_block<CS_MINK2_DIAMOND, kBuildRowBlocks>(
+      coords + d.coord_off, d.n, bits + d.bits_off, d.ld, ceil_div(d.n, 64),
+      (int64_t)((it >> 8) & 255u) * kBuildRowBlocks, it & 255u, cols[wave]);
 }
 
 template <int R>
@@ -316,7 +380,8 @@ cs_status launch_causal_matrix(int region, const double* coords, int64_t n, uint
 cs_status launch_build_batch(const double* coords, const BatchInst* inst, const uint32_t* items,
                              int64_t nitems, uint64_t* bits, hipStream_t st) {
   if (nitems <= 0) return CS_OK;
-  hipLaunchKernelGGL(k_build_batch, dim3((unsigned)ceil_div(nitems, kWavesPerBlock)),
+  if (nitems % (kBatchQueues * kWavesPerBlock) != 0) return CS_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(k_build_batch, dim3((unsigned)(nitems / kWavesPerBlock)),
                      dim3(64 * kWavesPerBlock), 0, st, coords, inst, items, nitems, bits);
   CS_LAUNCH_CHECK();
   return CS_OK;

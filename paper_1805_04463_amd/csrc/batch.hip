@@ -219,16 +219,18 @@ cs_status build_plan(int64_t count, const int64_t* n, int counter, int n_eps, co
     boff += d.n * d.ld;
     hoff += d.n - 1;
     const int64_t nb = ceil_div(d.n, 64);
-    // Builder items (row group g: row blocks kBuildRowBlocks g + r; column block bj) in
-    // patches of kBuildPatch x kBuildPatch blocks: a patch writes whole 128-byte lines of
-    // its rows' words and of its transposed words, so the lines are complete while the
+    // Builder items (row group g: row blocks kBuildRowBlocks g + r; column blocks bj0 + c)
+    // in patches of kBuildPatch x kBuildPatch blocks: a patch writes whole 128-byte lines
+    // of its rows' words and of its transposed words, so the lines are complete while the
     // XCD that builds the instance holds them in its L2.
+    static_assert(kBuildPatch % kBuildRowBlocks == 0 && kBuildPatch % kBuildColBlocks == 0 &&
+                      kBuildRowBlocks % kBuildColBlocks == 0, "builder items tile the patches");
     constexpr int64_t G = kBuildPatch / kBuildRowBlocks;  // row groups per patch
     for (int64_t pr = 0; pr * kBuildPatch < nb; ++pr)
       for (int64_t pc = pr; pc * kBuildPatch < nb; ++pc)
         for (int64_t g = pr * G; g < pr * G + G && g * kBuildRowBlocks < nb; ++g)
           for (int64_t bj = std::max(pc * kBuildPatch, g * kBuildRowBlocks);
-               bj < std::min((pc + 1) * kBuildPatch, nb); ++bj)
+               bj < std::min((pc + 1) * kBuildPatch, nb); bj += kBuildColBlocks)
             bitems[k].push_back((uint32_t)(k << 16 | g << 8 | bj));
     const int b = bucket_of(d.n);
     const BatchTile cfg = force ? *force

@@ -237,18 +237,18 @@ __device__ __attribute__((always_inline)) inline void row_words(
   for (int r = 0; r < RB; ++r) out[r] = ((uint64_t)half[r][1] << 32) | half[r][0];
 }
 
-// One wave: the 64x64 blocks (bi0 + r, bj), r = 0 .. RB-1, of an n-point matrix S with
-// stride ld, those with bi0 + r <= bj (bi0 <= bj; bi0 and bj are wave-uniform).  Lane l
-// owns rows i = 64 (bi0 + r) + l and collects their row words for the 64 column points
-// of block bj.  The transposed words (rows of block bj, columns of block bi0 + r) come
-// from a 64x64 bit transpose of each row word, so each unordered pair is tested once.
-// Row blocks below the diagonal (bi0 + r > bj) are tested but not written.  The wave
-// owning the last column block of a row block also zeroes that row block's padding words
+// One wave: the 64x64 blocks (bi0 + r, bj0 + c), r < RB, c < CB, of an n-point matrix S
+// with stride ld, those with bi0 + r <= bj0 + c < nb (bi0 <= bj0; both wave-uniform).
+// Lane l owns rows i = 64 (bi0 + r) + l and collects their row words for the 64 column
+// points of each block bj0 + c.  The transposed words (rows of block bj0 + c, columns of
+// block bi0 + r) come from a 64x64 bit transpose of each row word, so each unordered pair
+// is tested once.  Blocks below the diagonal are tested but not written.  The wave owning
+// the last column block of a row block also zeroes that row block's padding words
 // [nb, ld), so every word of S is written exactly once.
-template <int R, int RB>
+template <int R, int RB, int CB>
 __device__ __attribute__((always_inline)) inline void build_block(
     const double* __restrict__ coords, int64_t n, uint64_t* __restrict__ S, int64_t ld, int64_t nb,
-    int64_t bi0, int64_t bj, Pt<R>* cols) {
+    int64_t bi0, int64_t bj0, Pt<R>* cols) {
   const int lane = threadIdx.x & 63;
   Pt<R> pi[RB];
 #pragma unroll
@@ -256,31 +256,73 @@ __device__ __attribute__((always_inline)) inline void build_block(
     const int64_t i = (bi0 + r) * 64 + lane;
     pi[r] = load_pt(coords, n, i < n ? i : n - 1, (Pt<R>*)nullptr);
   }
-  uint64_t rows[RB];
-  if (bj * 64 + 64 <= n) row_words<R, true, RB>(coords, n, bj * 64, pi, cols, rows);
-  else row_words<R, false, RB>(coords, n, bj * 64, pi, cols, rows);
-  const int64_t j = bj * 64 + lane;
-  const bool jv = j < n;
-  const int64_t ncols = n - bj * 64;  // valid columns of this block (>= 1)
+  uint64_t rows[CB][RB];
 #pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    const int64_t bi = bi0 + r;
-    if (bi > bj) break;  // this and the later row blocks lie below the diagonal
-    const int64_t i = bi * 64 + lane;
-    const bool iv = i < n;
-    uint64_t row = rows[r];
-    if (ncols < 64) row &= (1ull << ncols) - 1ull;
-    if (bi == bj) row &= lane == 63 ? 0ull : (~0ull << (lane + 1));  // only j > i
-    if (!iv) row = 0;
-    const uint64_t col = wave_transpose64(row);  // lane l: row j's bits for columns of bi
-    if (bi == bj) {
-      if (iv) S[i * ld + bi] = row | col;
-    } else {
-      if (iv) S[i * ld + bj] = row;
-      if (jv) S[j * ld + bi] = col;
+  for (int c = 0; c < CB; ++c) {
+    const int64_t bj = bj0 + c;
+    if (bj >= nb) break;
+    if (bj * 64 + 64 <= n) row_words<R, true, RB>(coords, n, bj * 64, pi, cols, rows[c]);
+    else row_words<R, false, RB>(coords, n, bj * 64, pi, cols, rows[c]);
+    const int64_t ncols = n - bj * 64;  // valid columns of this block (>= 1)
+    if (ncols < 64)
+#pragma unroll
+      for (int r = 0; r < RB; ++r) rows[c][r] &= (1ull << ncols) - 1ull;
+  }
+  if constexpr (RB == 4 && CB == 2) {
+    if (bi0 + RB - 1 < bj0 && bj0 + 1 < nb) {
+      // Every block lies above the diagonal and every row is valid: a lane's two row words
+      // of row i (column blocks bj0, bj0 + 1) and its four transposed words of row j
+      // (column blocks bi0 .. bi0 + 3) are contiguous and 16-byte aligned (bj0 is even,
+      // bi0 a multiple of 4, rows start on 64-byte boundaries), so they go out as 16-byte
+      // stores instead of 8-byte ones.
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int64_t i = (bi0 + r) * 64 + lane;
+        *(uint4*)(S + i * ld + bj0) = make_uint4((uint32_t)rows[0][r], (uint32_t)(rows[0][r] >> 32),
+                                                 (uint32_t)rows[1][r], (uint32_t)(rows[1][r] >> 32));
+        if (bj0 + 1 == nb - 1)
+          for (int64_t w = nb; w < ld; ++w) S[i * ld + w] = 0;
+      }
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        uint64_t cw[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) cw[r] = wave_transpose64(rows[c][r]);
+        const int64_t j = (bj0 + c) * 64 + lane;
+        if (j < n) {
+          uint4* dst = (uint4*)(S + j * ld + bi0);
+          dst[0] = make_uint4((uint32_t)cw[0], (uint32_t)(cw[0] >> 32), (uint32_t)cw[1], (uint32_t)(cw[1] >> 32));
+          dst[1] = make_uint4((uint32_t)cw[2], (uint32_t)(cw[2] >> 32), (uint32_t)cw[3], (uint32_t)(cw[3] >> 32));
+        }
+      }
+      return;
     }
-    if (bj == nb - 1 && iv)
-      for (int64_t w = nb; w < ld; ++w) S[i * ld + w] = 0;
+  }
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const int64_t bj = bj0 + c;
+    if (bj >= nb) break;
+    const int64_t j = bj * 64 + lane;
+    const bool jv = j < n;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int64_t bi = bi0 + r;
+      if (bi > bj) break;  // this and the later row blocks lie below the diagonal
+      const int64_t i = bi * 64 + lane;
+      const bool iv = i < n;
+      uint64_t row = rows[c][r];
+      if (bi == bj) row &= lane == 63 ? 0ull : (~0ull << (lane + 1));  // only j > i
+      if (!iv) row = 0;
+      const uint64_t col = wave_transpose64(row);  // lane l: row j's bits for columns of bi
+      if (bi == bj) {
+        if (iv) S[i * ld + bi] = row | col;
+      } else {
+        if (iv) S[i * ld + bj] = row;
+        if (jv) S[j * ld + bi] = col;
+      }
+      if (bj == nb - 1 && iv)
+        for (int64_t w = nb; w < ld; ++w) S[i * ld + w] = 0;
+    }
   }
 }
 
@@ -322,13 +364,14 @@ __global__ __launch_bounds__(256) void k_build(const double* __restrict__ coords
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t bj = (px * kGroups + l % kGroups) * kWavesPerBlock + wave;
   if (bi >= nb || bj >= nb || bj < bi) return;  // wave-uniform exit; no block barriers below
-  build_block<R, 1>(coords, n, S, ld, nb, bi, bj, cols[kScalarColumns<R> ? 0 : wave]);
+  build_block<R, 1, 1>(coords, n, S, ld, nb, bi, bj, cols[kScalarColumns<R> ? 0 : wave]);
 }
 
-// Ensemble of 1+1 diamonds.  Work items are packed as instance << 16 | g << 8 | bj: row
-// blocks kBuildRowBlocks g + r against column block bj >= kBuildRowBlocks g.  Each
-// column point read from LDS serves kBuildRowBlocks rows of the lane, which takes the
-// blocks off the LDS bound of one row per lane.  The items form kBatchQueues lists of
+// Ensemble of 1+1 diamonds.  Work items are packed as instance << 16 | g << 8 | bj0: row
+// blocks kBuildRowBlocks g + r against column blocks bj0 + c, c < kBuildColBlocks, with
+// bj0 >= kBuildRowBlocks g a multiple of kBuildColBlocks.  Each column point read from LDS
+// serves kBuildRowBlocks rows of the lane, which takes the blocks off the LDS bound of one
+// row per lane, and the words of whole groups leave in 16-byte stores.  The items form kBatchQueues lists of
 // equal length (one per XCD, padded with kNoBuildItem); wave w of workgroup b takes
 // entry kBuildWaves (b div kBatchQueues) + w of list b mod kBatchQueues.
 static_assert(kWavesPerBlock == kBuildWaves, "ensemble builder lists are dealt per workgroup");
@@ -344,7 +387,7 @@ __global__ __launch_bounds__(256) void k_build_batch(const double* __restrict__ 
   const uint32_t it = items[t];
   if (it == kNoBuildItem) return;
   const BatchInst d = inst[it >> 16];
-  build_block<CS_MINK2_DIAMOND, kBuildRowBlocks>(
+  build_block<CS_MINK2_DIAMOND, kBuildRowBlocks, kBuildColBlocks>(
       coords + d.coord_off, d.n, bits + d.bits_off, d.ld, ceil_div(d.n, 64),
       (int64_t)((it >> 8) & 255u) * kBuildRowBlocks, it & 255u, cols[wave]);
 }

@@ -93,9 +93,10 @@ struct BatchInst {
 // Largest instance of an ensemble (its whole histogram fits the LDS bins, its sort
 // fits one workgroup's LDS).
 constexpr int64_t kBatchMaxN = 8192;
-// Ensemble builder: row blocks of 64 points per work item (one column block each), blocks
-// per patch side, waves per workgroup, and the padding entry of its per-XCD item lists.
+// Ensemble builder: row and column blocks of 64 points per work item, blocks per patch
+// side, waves per workgroup, and the padding entry of its per-XCD item lists.
 constexpr int kBuildRowBlocks = 4;
+constexpr int kBuildColBlocks = 2;
 constexpr int kBuildPatch = 16;
 constexpr int kBuildWaves = 4;
 constexpr uint32_t kNoBuildItem = 0xFFFFFFFFu;

@@ -257,30 +257,38 @@ __device__ __attribute__((always_inline)) inline void build_block(
     pi[r] = load_pt(coords, n, i < n ? i : n - 1, (Pt<R>*)nullptr);
   }
   uint64_t rows[CB][RB];
-#pragma unroll
-  for (int c = 0; c < CB; ++c) {
-    const int64_t bj = bj0 + c;
-    if (bj >= nb) break;
-    if (bj * 64 + 64 <= n) row_words<R, true, RB>(coords, n, bj * 64, pi, cols, rows[c]);
-    else row_words<R, false, RB>(coords, n, bj * 64, pi, cols, rows[c]);
-    const int64_t ncols = n - bj * 64;  // valid columns of this block (>= 1)
-    if (ncols < 64)
-#pragma unroll
-      for (int r = 0; r < RB; ++r) rows[c][r] &= (1ull << ncols) - 1ull;
+  if (bj0 * 64 + 64 <= n) row_words<R, true, RB>(coords, n, bj0 * 64, pi, cols, rows[0]);
+  else row_words<R, false, RB>(coords, n, bj0 * 64, pi, cols, rows[0]);
+  if constexpr (CB == 2) {
+    const int64_t bj = bj0 + 1;
+    if (bj < nb) {
+      if (bj * 64 + 64 <= n) row_words<R, true, RB>(coords, n, bj * 64, pi, cols, rows[1]);
+      else row_words<R, false, RB>(coords, n, bj * 64, pi, cols, rows[1]);
+    }
   }
-  if constexpr (RB == 4 && CB == 2) {
-    if (bi0 + RB - 1 < bj0 && bj0 + 1 < nb) {
-      // Every block lies above the diagonal and every row is valid: a lane's two row words
-      // of row i (column blocks bj0, bj0 + 1) and its four transposed words of row j
-      // (column blocks bi0 .. bi0 + 3) are contiguous and 16-byte aligned (bj0 is even,
-      // bi0 a multiple of 4, rows start on 64-byte boundaries), so they go out as 16-byte
+  if constexpr (RB == 4) {
+    if (bi0 + RB - 1 < bj0 && bj0 + CB - 1 < nb) {
+      // Every block lies above the diagonal and every row is valid: a lane's four
+      // transposed words of row j (column blocks bi0 .. bi0 + 3) are contiguous and 16-byte
+      // aligned (bi0 is a multiple of 4, rows start on 64-byte boundaries), and so are its
+      // two row words of row i with two column blocks (bj0 even), so they go out as 16-byte
       // stores instead of 8-byte ones.
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const int64_t ncols = n - (bj0 + c) * 64;  // valid columns of the block (>= 1)
+        if (ncols < 64)
+#pragma unroll
+          for (int r = 0; r < RB; ++r) rows[c][r] &= (1ull << ncols) - 1ull;
+      }
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const int64_t i = (bi0 + r) * 64 + lane;
-        *(uint4*)(S + i * ld + bj0) = make_uint4((uint32_t)rows[0][r], (uint32_t)(rows[0][r] >> 32),
-                                                 (uint32_t)rows[1][r], (uint32_t)(rows[1][r] >> 32));
-        if (bj0 + 1 == nb - 1)
+        if constexpr (CB == 2)
+          *(uint4*)(S + i * ld + bj0) = make_uint4((uint32_t)rows[0][r], (uint32_t)(rows[0][r] >> 32),
+                                                   (uint32_t)rows[1][r], (uint32_t)(rows[1][r] >> 32));
+        else
+          S[i * ld + bj0] = rows[0][r];
+        if (bj0 + CB - 1 == nb - 1)
           for (int64_t w = nb; w < ld; ++w) S[i * ld + w] = 0;
       }
 #pragma unroll
@@ -301,9 +309,10 @@ __device__ __attribute__((always_inline)) inline void build_block(
 #pragma unroll
   for (int c = 0; c < CB; ++c) {
     const int64_t bj = bj0 + c;
-    if (bj >= nb) break;
+    if (c > 0 && bj >= nb) break;
     const int64_t j = bj * 64 + lane;
     const bool jv = j < n;
+    const int64_t ncols = n - bj * 64;  // valid columns of this block (>= 1)
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       const int64_t bi = bi0 + r;
@@ -311,6 +320,7 @@ __device__ __attribute__((always_inline)) inline void build_block(
       const int64_t i = bi * 64 + lane;
       const bool iv = i < n;
       uint64_t row = rows[c][r];
+      if (ncols < 64) row &= (1ull << ncols) - 1ull;
       if (bi == bj) row &= lane == 63 ? 0ull : (~0ull << (lane + 1));  // only j > i
       if (!iv) row = 0;
       const uint64_t col = wave_transpose64(row);  // lane l: row j's bits for columns of bi
@@ -326,8 +336,9 @@ __device__ __attribute__((always_inline)) inline void build_block(
   }
 }
 
-// Patches of 16 x 16 blocks (1024 x 1024 points) of the upper triangle, 64 workgroups
-// each (16 block rows x 4 groups of 4 block columns).  Workgroups are dealt to the 8
+// Patches of 16 x 16 blocks (1024 x 1024 points) of the upper triangle, 64 / RB workgroups
+// each (16 / RB groups of RB block rows x 4 groups of 4 block columns; a wave takes RB row
+// blocks against one column block).  Workgroups are dealt to the 8
 // XCDs in turn, so the workgroups of patch p get ids 8 apart: a patch is built
 // inside one XCD, whose L2 then holds every 128-byte line of its row segments and of
 // its transposed segments until the line is complete, instead of sending partial lines
@@ -337,34 +348,39 @@ __device__ __attribute__((always_inline)) inline void build_block(
 #define CS_BUILD_PATCH 16
 #endif
 constexpr int kPatch = CS_BUILD_PATCH;                       // blocks per patch side
-constexpr int kGroups = kPatch / kWavesPerBlock;             // workgroups per patch row
-constexpr int kPatchWgs = kPatch * kGroups;                  // workgroups per patch
-// Grid rows of at most 64 rounds of 8 patches: a row stays far below 2^32 work-items.
-constexpr int64_t kRowWgs = 8 * kPatchWgs * 64;
+constexpr int kGroups = kPatch / kWavesPerBlock;             // column groups per patch
+template <int RB>
+constexpr int kPatchWgs = kPatch / RB * kGroups;             // workgroups per patch
+// Row blocks per wave: four where the column points are staged in LDS (each broadcast
+// read then serves four rows of a lane), from 8 patches up (n > 3072: below that, the
+// fewer, longer waves cost more latency than the LDS reads they save).
+template <int R>
+constexpr int kRowBlocks = kScalarColumns<R> ? 1 : 4;
 
 __device__ inline int64_t patch_row_start(int64_t r, int64_t P) { return r * P - r * (r - 1) / 2; }
 
-template <int R>
+template <int R, int RB>
 __global__ __launch_bounds__(256) void k_build(const double* __restrict__ coords, int64_t n,
                                                uint64_t* __restrict__ S, int64_t ld, int64_t nb,
                                                int64_t P, int64_t npatch) {
+  constexpr int PW = kPatchWgs<RB>;
   __shared__ Pt<R> cols[kScalarColumns<R> ? 1 : kWavesPerBlock][64];
   const int64_t g = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
   const bool dealt = npatch >= 8;
-  const int64_t p = dealt ? (g / (8 * kPatchWgs)) * 8 + (g & 7) : g / kPatchWgs;
+  const int64_t p = dealt ? (g / (8 * PW)) * 8 + (g & 7) : g / PW;
   if (p >= npatch) return;
-  const int l = (int)(dealt ? (g >> 3) % kPatchWgs : g % kPatchWgs);
+  const int l = (int)(dealt ? (g >> 3) % PW : g % PW);
   // smaller root of r^2 - (2P+1) r + 2p = 0, then exact correction
   const double s2 = 2.0 * (double)P + 1.0;
   int64_t py = (int64_t)((s2 - sqrt(s2 * s2 - 8.0 * (double)p)) * 0.5);
   while (py > 0 && patch_row_start(py, P) > p) --py;
   while (patch_row_start(py + 1, P) <= p) ++py;
   const int64_t px = py + (p - patch_row_start(py, P));
-  const int64_t bi = py * kPatch + l / kGroups;
+  const int64_t bi = py * kPatch + RB * (l / kGroups);
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t bj = (px * kGroups + l % kGroups) * kWavesPerBlock + wave;
   if (bi >= nb || bj >= nb || bj < bi) return;  // wave-uniform exit; no block barriers below
-  build_block<R, 1, 1>(coords, n, S, ld, nb, bi, bj, cols[kScalarColumns<R> ? 0 : wave]);
+  build_block<R, RB, 1>(coords, n, S, ld, nb, bi, bj, cols[kScalarColumns<R> ? 0 : wave]);
 }
 
 // Ensemble of 1+1 diamonds.  Work items are packed as instance << 16 | g << 8 | bj0: row
@@ -392,18 +408,28 @@ __global__ __launch_bounds__(256) void k_build_batch(const double* __restrict__ 
       (int64_t)((it >> 8) & 255u) * kBuildRowBlocks, it & 255u, cols[wave]);
 }
 
+template <int R, int RB>
+cs_status launch_build_rb(const double* coords, int64_t n, uint64_t* S, int64_t ld, int64_t nb,
+                          int64_t P, int64_t npatch, hipStream_t st) {
+  // Grid rows of at most 64 rounds of 8 patches: a row stays far below 2^32 work-items.
+  constexpr int PW = kPatchWgs<RB>;
+  const int64_t rounds = ceil_div(npatch, 8);  // nb <= 65535: at most 2^20 rounds
+  const dim3 grid = npatch >= 8 ? dim3((unsigned)(8 * PW * std::min<int64_t>(rounds, 64)),
+                                       (unsigned)ceil_div(rounds, 64))
+                                : dim3((unsigned)(PW * npatch));
+  hipLaunchKernelGGL((k_build<R, RB>), grid, dim3(64 * kWavesPerBlock), 0, st, coords, n, S, ld, nb,
+                     P, npatch);
+  CS_LAUNCH_CHECK();
+  return CS_OK;
+}
+
 template <int R>
 cs_status launch_build(const double* coords, int64_t n, uint64_t* S, int64_t ld, hipStream_t st) {
   const int64_t nb = ceil_div(n, 64);
   const int64_t P = ceil_div(nb, kPatch), npatch = P * (P + 1) / 2;
-  const int64_t rounds = ceil_div(npatch, 8);  // nb <= 65535: at most 2^20 rounds
-  const dim3 grid = npatch >= 8 ? dim3((unsigned)(8 * kPatchWgs * std::min<int64_t>(rounds, 64)),
-                                       (unsigned)ceil_div(rounds, 64))
-                                : dim3((unsigned)(kPatchWgs * npatch));
-  hipLaunchKernelGGL(k_build<R>, grid, dim3(64 * kWavesPerBlock), 0, st, coords, n, S, ld, nb, P,
-                     npatch);
-  CS_LAUNCH_CHECK();
-  return CS_OK;
+  if (kRowBlocks<R> > 1 && npatch >= 8)
+    return launch_build_rb<R, kRowBlocks<R>>(coords, n, S, ld, nb, P, npatch, st);
+  return launch_build_rb<R, 1>(coords, n, S, ld, nb, P, npatch, st);
 }
 
 }  // namespace

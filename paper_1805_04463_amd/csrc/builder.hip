@@ -351,11 +351,11 @@ constexpr int kPatch = CS_BUILD_PATCH;                       // blocks per patch
 constexpr int kGroups = kPatch / kWavesPerBlock;             // column groups per patch
 template <int RB>
 constexpr int kPatchWgs = kPatch / RB * kGroups;             // workgroups per patch
-// Row blocks per wave: four where the column points are staged in LDS (each broadcast
-// read then serves four rows of a lane), from 8 patches up (n > 3072: below that, the
-// fewer, longer waves cost more latency than the LDS reads they save).
+// Row blocks per wave, from 8 patches up (n > 3072: below that, the fewer, longer waves
+// cost more latency than they save): four, so that each column point read from LDS (or
+// loaded into SGPRs) serves four rows of a lane.
 template <int R>
-constexpr int kRowBlocks = kScalarColumns<R> ? 1 : 4;
+constexpr int kRowBlocks = 4;
 
 __device__ inline int64_t patch_row_start(int64_t r, int64_t P) { return r * P - r * (r - 1) / 2; }
 

@@ -446,31 +446,33 @@ cs_status bitonic_sort(uint64_t* keys, uint32_t* gens, int64_t P, hipStream_t st
 }
 
 // ---------------------------------------------------------------------------
-// Ensemble of 1+1 diamonds: one workgroup per instance (n <= 8192).  Keys are
-// sorted in LDS; the sorted coordinates are then regenerated from the sorted
-// generation indices (the generator is counter-based), so no raw copy is kept.
+// Ensemble of 1+1 diamonds: one workgroup per instance (n <= 8192).  The time order is
+// (key, generation index) with the 54-bit key of the single-instance path.  The LDS sort
+// runs on one 64-bit word per point, the key's top 32 bits above the index, so each
+// compare-exchange moves 16 bytes instead of 24; points whose top key bits tie (about
+// one instance in thirty has such a pair) form runs that a second pass puts in
+// (key, index) order, with the keys regenerated from the indices (the generator is
+// counter-based).  The sorted coordinates are then regenerated the same way, so no raw
+// copy is kept.
 // ---------------------------------------------------------------------------
 constexpr int kBatchSortThreads = 1024;
+constexpr int kBatchKeyShift = 22;  // 54-bit keys: the top 32 bits go into the sort word
+
+__device__ inline uint64_t mink2_key(uint64_t skey, uint64_t g) {
+  return (sm_output(skey, 2 * g) >> 11) + (sm_output(skey, 2 * g + 1) >> 11);
+}
 
 __global__ __launch_bounds__(kBatchSortThreads) void k_sprinkle_mink2_batch(
     const uint64_t* __restrict__ seeds, const BatchInst* __restrict__ inst,
     double* __restrict__ coords) {
-  __shared__ uint64_t sk[kBatchMaxN];
-  __shared__ uint32_t sg[kBatchMaxN];
+  __shared__ uint64_t sw[kBatchMaxN];  // key >> kBatchKeyShift << 32 | generation index
   const BatchInst d = inst[blockIdx.x];
   const int n = (int)d.n;
   int P = 2;
   while (P < n) P <<= 1;
   const uint64_t skey = sm_stream_key(seeds[blockIdx.x], kStreamMink2);
-  for (int g = threadIdx.x; g < P; g += kBatchSortThreads) {
-    if (g < n) {
-      sk[g] = (sm_output(skey, 2 * (uint64_t)g) >> 11) + (sm_output(skey, 2 * (uint64_t)g + 1) >> 11);
-      sg[g] = (uint32_t)g;
-    } else {
-      sk[g] = ~0ull;
-      sg[g] = 0xFFFFFFFFu;
-    }
-  }
+  for (int g = threadIdx.x; g < P; g += kBatchSortThreads)
+    sw[g] = g < n ? (mink2_key(skey, (uint64_t)g) >> kBatchKeyShift) << 32 | (uint32_t)g : ~0ull;
   bool wide = true;  // the previous step (or the load) crossed 128-element blocks
   for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
@@ -480,15 +482,39 @@ __global__ __launch_bounds__(kBatchSortThreads) void k_sprinkle_mink2_batch(
       wide = j >= 128;
       for (int t = threadIdx.x; t < P / 2; t += kBatchSortThreads) {
         const int i = 2 * t - (t & (j - 1));
-        cmp_swap_lds(sk, sg, i, i + j, (i & k) == 0);
+        const uint64_t x = sw[i], y = sw[i + j];
+        if ((x > y) == ((i & k) == 0)) {
+          sw[i] = y;
+          sw[i + j] = x;
+        }
       }
+    }
+  }
+  __syncthreads();
+  // Runs of equal top key bits are in index order; put each in (key, index) order.
+  for (int i = threadIdx.x; i < n; i += kBatchSortThreads) {
+    const uint32_t h = (uint32_t)(sw[i] >> 32);
+    const bool start = i == 0 || (uint32_t)(sw[i - 1] >> 32) != h;
+    if (!start || i + 1 >= n || (uint32_t)(sw[i + 1] >> 32) != h) continue;
+    int e = i + 2;
+    while (e < n && (uint32_t)(sw[e] >> 32) == h) ++e;
+    for (int a = i + 1; a < e; ++a) {  // insertion sort of the run [i, e)
+      const uint64_t x = sw[a];
+      const uint64_t kx = mink2_key(skey, (uint32_t)x);
+      int b = a - 1;
+      for (; b >= i; --b) {
+        const uint64_t kb = mink2_key(skey, (uint32_t)sw[b]);
+        if (kb < kx || (kb == kx && (uint32_t)sw[b] < (uint32_t)x)) break;
+        sw[b + 1] = sw[b];
+      }
+      sw[b + 1] = x;
     }
   }
   __syncthreads();
   double* cu = coords + d.coord_off;
   double* cv = cu + n;
   for (int i = threadIdx.x; i < n; i += kBatchSortThreads) {
-    const uint64_t g = sg[i];
+    const uint64_t g = (uint32_t)sw[i];
     cu[i] = (double)(sm_output(skey, 2 * g) >> 11) * 0x1.0p-53;
     cv[i] = (double)(sm_output(skey, 2 * g + 1) >> 11) * 0x1.0p-53;
   }

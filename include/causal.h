@@ -279,6 +279,15 @@ cs_status cs_batch_plan(int64_t count, const int64_t *n /* host */, int counter,
 size_t cs_batch_workspace_bytes(cs_batch_plan_handle plan);
 int64_t cs_batch_hist_len(cs_batch_plan_handle plan);
 int64_t cs_batch_hist_offset(cs_batch_plan_handle plan, int64_t k);
+/*
+ * Where a run leaves instance k's intermediate results in the caller's workspace: byte
+ * offsets of its time-ordered coordinates (u then v, n[k] doubles each, as
+ * cs_sprinkle writes them) and of its packed matrix (n[k] rows of cs_ld_words(n[k])
+ * uint64 words, as cs_causal_matrix writes it).  -1 for a null plan or k out of range.
+ * The contents are valid after a run until the workspace is reused.
+ */
+int64_t cs_batch_coords_offset(cs_batch_plan_handle plan, int64_t k);
+int64_t cs_batch_bits_offset(cs_batch_plan_handle plan, int64_t k);
 cs_status cs_batch_run(cs_batch_plan_handle plan, const uint64_t *seeds, uint64_t *hist,
                        double *actions, void *workspace, size_t workspace_bytes, void *stream);
 cs_status cs_batch_free(cs_batch_plan_handle plan);

@@ -25,8 +25,8 @@ SYMBOLS = [
     "cs_coord_planes", "cs_ld_words", "cs_status_string", "cs_sprinkle_workspace_bytes",
     "cs_sprinkle", "cs_causal_matrix", "cs_histogram_workspace_bytes", "cs_interval_histogram",
     "cs_action", "cs_batch_plan", "cs_batch_workspace_bytes", "cs_batch_hist_len",
-    "cs_batch_hist_offset", "cs_batch_run", "cs_batch_free", "cs_batch_graph_create",
-    "cs_batch_graph_launch", "cs_batch_graph_destroy", "cs_autotune", "cs_measure_mfma_peak",
+    "cs_batch_hist_offset", "cs_batch_coords_offset", "cs_batch_bits_offset", "cs_batch_run",
+    "cs_batch_free", "cs_batch_graph_create", "cs_batch_graph_launch", "cs_batch_graph_destroy", "cs_autotune", "cs_measure_mfma_peak",
     "cs_dalembertian_workspace_bytes", "cs_dalembertian", "cs_longest_chain_workspace_bytes",
     "cs_longest_chain", "cs_degrees", "cs_interval_histogram_noalloc",
 ]
@@ -68,6 +68,8 @@ def lib():
             "cs_batch_workspace_bytes": (sz, [p]),
             "cs_batch_hist_len": (i64, [p]),
             "cs_batch_hist_offset": (i64, [p, i64]),
+            "cs_batch_coords_offset": (i64, [p, i64]),
+            "cs_batch_bits_offset": (i64, [p, i64]),
             "cs_batch_run": (c_int, [p, p, p, p, p, sz, p]),
             "cs_batch_free": (c_int, [p]),
             "cs_batch_graph_create": (c_int, [p, p, p, p, p, sz, ctypes.POINTER(p)]),
@@ -338,6 +340,9 @@ class BatchPlan:
         self.ws_bytes = lib().cs_batch_workspace_bytes(h)
         self.hist_len = lib().cs_batch_hist_len(h)
         self.offsets = [lib().cs_batch_hist_offset(h, k) for k in range(self.count)]
+        # byte offsets of each instance's coordinates and matrix in the workspace
+        self.coords_offsets = [lib().cs_batch_coords_offset(h, k) for k in range(self.count)]
+        self.bits_offsets = [lib().cs_batch_bits_offset(h, k) for k in range(self.count)]
 
     def _buffers(self, seeds, hist, actions, workspace):
         ptrs = (_need(seeds, "seeds", _WORDS, numel=self.count),

@@ -402,6 +402,16 @@ int64_t cs_batch_hist_offset(cs_batch_plan_handle plan, int64_t k) {
   return plan->inst[k].hist_off;
 }
 
+int64_t cs_batch_coords_offset(cs_batch_plan_handle plan, int64_t k) {
+  if (!plan || k < 0 || k >= plan->count) return -1;
+  return (int64_t)plan->off_coords + (int64_t)sizeof(double) * plan->inst[k].coord_off;
+}
+
+int64_t cs_batch_bits_offset(cs_batch_plan_handle plan, int64_t k) {
+  if (!plan || k < 0 || k >= plan->count) return -1;
+  return (int64_t)plan->off_bits + (int64_t)sizeof(uint64_t) * plan->inst[k].bits_off;
+}
+
 cs_status cs_batch_run(cs_batch_plan_handle plan, const uint64_t* seeds, uint64_t* hist,
                        double* actions, void* workspace, size_t workspace_bytes, void* stream) {
   if (!plan || !seeds || !hist || !workspace || (plan->n_eps > 0 && !actions))

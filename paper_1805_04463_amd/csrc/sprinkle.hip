@@ -427,6 +427,40 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_place(const uint64_t* __r
     for (int p = s; p < planes; p += kRankSplit) coords[(int64_t)p * n + lt] = raw[(int64_t)p * n + g];
 }
 
+// The 1+1 diamond's time key of draw g (see k_sprinkle_mink2).
+__device__ inline uint64_t mink2_key(uint64_t skey, uint64_t g) {
+  return (sm_output(skey, 2 * g) >> 11) + (sm_output(skey, 2 * g + 1) >> 11);
+}
+
+// 1+1 diamonds up to kRankMaxN points: k_rank_place with the keys and coordinates taken
+// straight from the counter-based generator, so the draws, the ranks and the placement
+// are one launch.
+__global__ __launch_bounds__(kRankThreads) void k_rank_place_mink2(uint64_t skey, int64_t n,
+                                                                   double* __restrict__ coords) {
+  __shared__ uint64_t sk[kRankChunk];
+  const int s = threadIdx.x & (kRankSplit - 1);
+  const int64_t g = (int64_t)blockIdx.x * kRankPer + threadIdx.x / kRankSplit;
+  const bool live = g < n;
+  const uint64_t ku = live ? sm_output(skey, 2 * (uint64_t)g) >> 11 : 0ull;
+  const uint64_t kv = live ? sm_output(skey, 2 * (uint64_t)g + 1) >> 11 : 0ull;
+  const uint64_t kg = ku + kv;
+  uint32_t before = 0;  // elements h with (key_h, h) < (key_g, g)
+  for (int64_t base = 0; base < n; base += kRankChunk) {
+    const int m = (int)(n - base < kRankChunk ? n - base : kRankChunk);
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += kRankThreads) sk[i] = mink2_key(skey, (uint64_t)(base + i));
+    __syncthreads();
+    const int gi = (int)(g - base);  // g's index within the chunk (any value if outside)
+#pragma unroll 8
+    for (int i = s; i < m; i += kRankSplit) {
+      const uint64_t kh = sk[i];
+      before += (kh < kg || (kh == kg && i < gi)) ? 1u : 0u;
+    }
+  }
+  const uint32_t lt = rank_lane_sum(before);
+  if (live && s < 2) coords[(int64_t)s * n + lt] = (double)(s == 0 ? ku : kv) * 0x1.0p-53;
+}
+
 cs_status bitonic_sort(uint64_t* keys, uint32_t* gens, int64_t P, hipStream_t st) {
   const int CH = (int)(P < kSortChunk ? P : kSortChunk);
   const unsigned nchunks = (unsigned)(P / CH);
@@ -457,10 +491,6 @@ cs_status bitonic_sort(uint64_t* keys, uint32_t* gens, int64_t P, hipStream_t st
 // ---------------------------------------------------------------------------
 constexpr int kBatchSortThreads = 1024;
 constexpr int kBatchKeyShift = 22;  // 54-bit keys: the top 32 bits go into the sort word
-
-__device__ inline uint64_t mink2_key(uint64_t skey, uint64_t g) {
-  return (sm_output(skey, 2 * g) >> 11) + (sm_output(skey, 2 * g + 1) >> 11);
-}
 
 __global__ __launch_bounds__(kBatchSortThreads) void k_sprinkle_mink2_batch(
     const uint64_t* __restrict__ seeds, const BatchInst* __restrict__ inst,
@@ -531,6 +561,12 @@ cs_status launch_sprinkle(int region, double eta0, uint64_t seed, int64_t n, dou
   const int64_t P = pow2_at_least(n);
   const int planes = coord_planes(region);
   const unsigned gridP = (unsigned)ceil_div(P, kBlock);
+  if (region == CS_MINK2_DIAMOND && n <= kRankMaxN) {
+    hipLaunchKernelGGL(k_rank_place_mink2, dim3((unsigned)ceil_div(n, kRankPer)), dim3(kRankThreads),
+                       0, st, sm_stream_key(seed, kStreamMink2), n, coords);
+    CS_LAUNCH_CHECK();
+    return CS_OK;
+  }
   if (region == CS_MINK2_DIAMOND) {
     hipLaunchKernelGGL(k_sprinkle_mink2, dim3(gridP), dim3(kBlock), 0, st,
                        sm_stream_key(seed, kStreamMink2), n, P, w.raw, w.keys, w.gens);

@@ -294,8 +294,8 @@ cs_status cs_batch_free(cs_batch_plan_handle plan);
 
 /*
  * HIP graph of one cs_batch_run with these buffers, captured on an internal stream and
- * instantiated (so the graph replays the same five launches: fills, sprinkle, build,
- * count, action).  graph_exec receives an opaque hipGraphExec_t owned by the caller:
+ * instantiated (so the graph replays the same four launches: sprinkle, which also clears
+ * the histograms and the work counters, build, count, action).  graph_exec receives an opaque hipGraphExec_t owned by the caller:
  * launch it with cs_batch_graph_launch on any stream, release it with
  * cs_batch_graph_destroy.  The buffers must stay valid while the graph is in use.
  */

@@ -1,9 +1,9 @@
 // Ensembles of independent 1+1 diamonds: plan, run, HIP-graph capture and the tile
 // autotuner.  (The thesis averages its action measurements over ensembles of
-// causal sets; here the ensemble is one pipeline of five launches.)
+// causal sets; here the ensemble is one pipeline of four launches.)
 //
 // Plan: per-instance offsets into three concatenated buffers (coordinates, matrices,
-// histograms), the builder's work list (one item per 64x64 block pair bi <= bj) and
+// histograms), the builder's work lists (items of 4x2 blocks of 64x64, per XCD) and
 // the counters' work lists (one item per row panel I of output tiles, i.e. all tiles
 // (I, J >= I) of an instance, so a workgroup keeps one instance's histogram in LDS for
 // a whole panel), dealt to one queue per XCD: whole instances, largest first to the
@@ -423,10 +423,10 @@ cs_status cs_batch_run(cs_batch_plan_handle plan, const uint64_t* seeds, uint64_
   double* coords = (double*)(ws + plan->off_coords);
   uint64_t* bits = (uint64_t*)(ws + plan->off_bits);
   cs_status s;
-  if ((s = launch_fill_u64((uint64_t*)ctr, kMaxSlots * kBatchQueues / 2, 0, st)) != CS_OK)
+  // the sprinkle kernel also clears the histograms and the work counters
+  if ((s = launch_sprinkle_batch(seeds, plan->d_inst, plan->count, coords, hist, (uint64_t*)ctr,
+                                 kMaxSlots * kBatchQueues / 2, st)) != CS_OK)
     return s;
-  if ((s = launch_fill_u64(hist, plan->hist_len, 0, st)) != CS_OK) return s;
-  if ((s = launch_sprinkle_batch(seeds, plan->d_inst, plan->count, coords, st)) != CS_OK) return s;
   if ((s = launch_build_batch(coords, plan->d_inst, plan->d_build, plan->n_build, bits, st)) != CS_OK)
     return s;
   if ((s = run_counts(plan, bits, hist, ctr, st)) != CS_OK) return s;

@@ -135,7 +135,8 @@ cs_status scratch_for_current_device(void** out);
 
 // Ensemble pieces (1+1 diamonds).
 cs_status launch_sprinkle_batch(const uint64_t* seeds, const BatchInst* inst, int64_t count,
-                                double* coords, hipStream_t st);
+                                double* coords, uint64_t* hist, uint64_t* zero, int nzero,
+                                hipStream_t st);
 cs_status launch_build_batch(const double* coords, const BatchInst* inst,
                              const uint32_t* items, int64_t nitems, uint64_t* bits,
                              hipStream_t st);

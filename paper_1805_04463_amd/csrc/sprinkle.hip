@@ -494,10 +494,16 @@ constexpr int kBatchKeyShift = 22;  // 54-bit keys: the top 32 bits go into the 
 
 __global__ __launch_bounds__(kBatchSortThreads) void k_sprinkle_mink2_batch(
     const uint64_t* __restrict__ seeds, const BatchInst* __restrict__ inst,
-    double* __restrict__ coords) {
+    double* __restrict__ coords, uint64_t* __restrict__ hist, uint64_t* __restrict__ zero,
+    int nzero) {
   __shared__ uint64_t sw[kBatchMaxN];  // key >> kBatchKeyShift << 32 | generation index
   const BatchInst d = inst[blockIdx.x];
   const int n = (int)d.n;
+  // The pipeline's later kernels accumulate into the instance's histogram and take work
+  // from counters: both start at zero, cleared here instead of by launches of their own.
+  for (int m = threadIdx.x; m < n - 1; m += kBatchSortThreads) hist[d.hist_off + m] = 0;
+  if (blockIdx.x == 0)
+    for (int w = threadIdx.x; w < nzero; w += kBatchSortThreads) zero[w] = 0;
   int P = 2;
   while (P < n) P <<= 1;
   const uint64_t skey = sm_stream_key(seeds[blockIdx.x], kStreamMink2);
@@ -623,10 +629,11 @@ cs_status launch_sprinkle(int region, double eta0, uint64_t seed, int64_t n, dou
 }
 
 cs_status launch_sprinkle_batch(const uint64_t* seeds, const BatchInst* inst, int64_t count,
-                                double* coords, hipStream_t st) {
+                                double* coords, uint64_t* hist, uint64_t* zero, int nzero,
+                                hipStream_t st) {
   if (count <= 0) return CS_OK;
   hipLaunchKernelGGL(k_sprinkle_mink2_batch, dim3((unsigned)count), dim3(kBatchSortThreads), 0, st,
-                     seeds, inst, coords);
+                     seeds, inst, coords, hist, zero, nzero);
   CS_LAUNCH_CHECK();
   return CS_OK;
 }

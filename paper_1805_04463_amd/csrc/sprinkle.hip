@@ -509,22 +509,68 @@ __global__ __launch_bounds__(kBatchSortThreads) void k_sprinkle_mink2_batch(
   const uint64_t skey = sm_stream_key(seeds[blockIdx.x], kStreamMink2);
   for (int g = threadIdx.x; g < P; g += kBatchSortThreads)
     sw[g] = g < n ? (mink2_key(skey, (uint64_t)g) >> kBatchKeyShift) << 32 | (uint32_t)g : ~0ull;
+  // One compare-exchange step of distance j in merge stage k through LDS: pairs t,
+  // t + 1024, ... of thread t; with j <= 64 every 128-element block is still worked by
+  // one wave (block b by wave b mod 16), so the step only synchronises the wave.
   bool wide = true;  // the previous step (or the load) crossed 128-element blocks
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      // pairs t, t + 1024, ... of thread t: with j <= 64 every 128-element block is
-      // still worked by one wave (block b by wave b mod 16)
-      bitonic_step_sync(wide || j >= 128);
-      wide = j >= 128;
-      for (int t = threadIdx.x; t < P / 2; t += kBatchSortThreads) {
-        const int i = 2 * t - (t & (j - 1));
-        const uint64_t x = sw[i], y = sw[i + j];
-        if ((x > y) == ((i & k) == 0)) {
-          sw[i] = y;
-          sw[i + j] = x;
-        }
+  auto lds_step = [&](int k, int j) {
+    bitonic_step_sync(wide || j >= 128);
+    wide = j >= 128;
+    for (int t = threadIdx.x; t < P / 2; t += kBatchSortThreads) {
+      const int i = 2 * t - (t & (j - 1));
+      const uint64_t x = sw[i], y = sw[i + j];
+      if ((x > y) == ((i & k) == 0)) {
+        sw[i] = y;
+        sw[i + j] = x;
       }
     }
+  };
+  // The steps of distance 4, 2 and 1 of stage k (and, with k = 0, the whole of stages
+  // 2, 4 and 8) on 8-element chunks held in registers: one LDS read and write of each
+  // element instead of three steps.  A chunk's 8 elements share the direction bit of
+  // every stage k >= 8.
+  auto chunk_steps = [&](int k) {
+    __syncthreads();
+    for (int c = threadIdx.x; c < P / 8; c += kBatchSortThreads) {
+      uint64_t v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = sw[8 * c + e];
+      auto cx = [&](int e, int j, bool asc) {
+        const uint64_t x = v[e], y = v[e + j];
+        const bool sw_ = (x > y) == asc;
+        v[e] = sw_ ? y : x;
+        v[e + j] = sw_ ? x : y;
+      };
+      if (k == 0) {
+#pragma unroll
+        for (int kk = 2; kk <= 8; kk <<= 1)
+#pragma unroll
+          for (int j = kk >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              if ((e & j) == 0) cx(e, j, ((8 * c + e) & kk) == 0);
+      } else {
+        const bool asc = ((8 * c) & k) == 0;
+#pragma unroll
+        for (int j = 4; j > 0; j >>= 1)
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if ((e & j) == 0) cx(e, j, asc);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sw[8 * c + e] = v[e];
+    }
+    wide = true;
+  };
+  if (P >= 8) {
+    chunk_steps(0);
+    for (int k = 16; k <= P; k <<= 1) {
+      for (int j = k >> 1; j >= 8; j >>= 1) lds_step(k, j);
+      chunk_steps(k);
+    }
+  } else {
+    for (int k = 2; k <= P; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) lds_step(k, j);
   }
   __syncthreads();
   // Runs of equal top key bits are in index order; put each in (key, index) order.
